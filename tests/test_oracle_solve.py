@@ -1,0 +1,159 @@
+"""Pins of the oracle's global system and solves (eqs. (1)-(4)).
+
+* closed form: normally incident plane wave in a waveguide (exact impedance
+  condition), exact 1D discrete solution for degree 0, h-convergence rates;
+* brute force: dense complex and dense real-block solves on tiny meshes;
+* invariants: power balance, global discrete de Rham (A grad = 0), DoF and nnz
+  counts from the closed-form formulas.
+"""
+import itertools
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import closed_form, fe, system
+from oracle.mesh import BoxMesh, expected_counts
+from oracle.system import Problem
+
+
+def waveguide(dim, m, p, omega=10.0):
+    inc = closed_form.WAVEGUIDE_INC_2D if dim == 2 else closed_form.WAVEGUIDE_INC_3D
+    return Problem(dim=dim, n=(m,) * dim + (1,) * (3 - dim), p=p, omega=omega, inc_faces=inc)
+
+
+@pytest.mark.parametrize("m", [8, 16, 32])
+def test_waveguide_lowest_order_matches_discrete_closed_form(m):
+    s = system.assemble(waveguide(2, m, 0))
+    E = system.solve_lu(s)
+    u = closed_form.waveguide_p0_nodal(m, 10.0)
+    mesh = s.mesh
+    h = 1.0 / m
+    for j in range(m):
+        for i in range(m + 1):
+            dof = mesh.edge_dofs(1, mesh.edge_id(1, i, j))[0]
+            assert abs(E[dof] - h * u[i]) < 1e-12 * h
+    xe = E[mesh.edge_off[0]:mesh.edge_off[1]]
+    assert np.abs(xe).max() < 1e-13
+
+
+@pytest.mark.parametrize("dim,p,sizes", [(2, 0, (8, 16, 32)), (2, 1, (8, 16, 32)), (2, 2, (8, 16, 32)),
+                                          (3, 0, (4, 8, 16)), (3, 1, (2, 4, 8))])
+def test_waveguide_convergence_rates(dim, p, sizes):
+    """||E - E_h||_L2 = O(h^{p+2}) (tensor elements on this field), ||curl(.)|| = O(h^{p+1})."""
+    omega = 10.0 if dim == 2 else 4.0
+    errs = []
+    for m in sizes:
+        s = system.assemble(waveguide(dim, m, p, omega))
+        E = system.solve_lu(s)
+        errs.append(system.field_l2(s, E, closed_form.plane_wave(dim, omega)))
+    errs = np.array(errs)
+    r0 = np.log2(errs[-2, 0] / errs[-1, 0])
+    r1 = np.log2(errs[-2, 1] / errs[-1, 1])
+    assert abs(r1 - (p + 1)) < 0.15, (r0, r1)
+    assert r0 > p + 1.8 or (dim == 3 and r0 > p + 0.85), (r0, r1)
+
+
+TINY = [(2, m, p) for m in (1, 2, 4) for p in (0, 1, 2)] + [(3, m, p) for m in (1, 2) for p in (0, 1)]
+
+
+@pytest.mark.parametrize("dim,m,p", TINY)
+def test_dense_solve_equals_lu_and_real_block(dim, m, p):
+    rng = np.random.default_rng(m * 10 + p)
+    n = (m,) * dim + (1,) * (3 - dim)
+    mu = rng.uniform(1, 2, m ** dim)
+    th = 0.4
+    pr = Problem(dim=dim, n=n, p=p, omega=7.0, mu=mu, kappa=1.3,
+                 inc_dir=(np.cos(th), np.sin(th), 0.0), inc_pol=(-np.sin(th), np.cos(th), 0.2j))
+    s = system.assemble(pr)
+    E1 = system.solve_lu(s)
+    E2 = system.solve_dense(s)
+    assert np.linalg.norm(E1 - E2) <= 1e-12 * np.linalg.norm(E2)
+    Ab, f = system.block_real(s)
+    x = np.linalg.solve(Ab.toarray(), f)
+    nF = len(s.F)
+    assert np.linalg.norm(x[:nF] + 1j * x[nF:] - E2[s.F]) <= 1e-12 * np.linalg.norm(E2)
+    # power balance: k w E^H M_inf E = Im(g_D^H (S E)_D)
+    R = s.S @ E2
+    lhs = pr.kappa * pr.omega * np.real(np.vdot(E2, s.Minf @ E2))
+    rhs = np.imag(np.vdot(s.gD, R[s.D]))
+    assert abs(lhs - rhs) <= 1e-10 * max(abs(lhs), 1e-300)
+    assert np.abs(R[s.F]).max() <= 1e-10 * np.abs(R).max()
+
+
+def _l2_project_gradient(s, grad):
+    """Nedelec DoFs of grad(psi) by the global L2 projection M g = (grad psi, phi)."""
+    mesh = s.mesh
+    d, p = mesh.dim, mesh.p
+    pts, w = fe.tensor_quad(d, p + 3)
+    vals, _ = fe.ref_eval(d, p, pts)
+    pv = vals / mesh.h[None, :, None]
+    b = np.zeros(mesh.n_dofs)
+    T = mesh.table()
+    for c in range(mesh.n_cells):
+        X = mesh.cell_origin(c)[None, :] + pts * mesh.h[None, :]
+        b_loc = np.einsum("uaq,qa,q->u", pv, grad(X), w) * np.prod(mesh.h)
+        np.add.at(b, T[c], b_loc)
+    return spla.spsolve(s.M.tocsc(), b)
+
+
+@pytest.mark.parametrize("dim,m,p", [(2, 3, 0), (2, 3, 1), (2, 2, 2), (3, 2, 0), (3, 2, 1)])
+def test_global_discrete_de_rham(dim, m, p):
+    """Gradients of continuous Q_{p+1} functions lie in N_h^p and A g = 0, K g = -w^2 M g."""
+    k = p + 1
+    coef = np.random.default_rng(3).standard_normal(dim)
+
+    def grad(X):
+        G = np.zeros_like(X)
+        for a in range(dim):
+            G[:, a] = coef[a] * k * X[:, a] ** (k - 1)
+            for b in range(dim):
+                if b != a:
+                    G[:, a] *= 1.0
+        # psi = sum_a coef_a x_a^k + x_0^k x_1^k (mixed term)
+        G[:, 0] += k * X[:, 0] ** (k - 1) * X[:, 1] ** k
+        G[:, 1] += k * X[:, 1] ** (k - 1) * X[:, 0] ** k
+        return G
+
+    pr = Problem(dim=dim, n=(m,) * dim + (1,) * (3 - dim), p=p, omega=3.0)
+    s = system.assemble(pr)
+    g = _l2_project_gradient(s, grad)
+    assert np.abs(s.A @ g).max() < 1e-10 * np.abs(s.A).max() * np.abs(g).max()
+    r = s.K @ g + pr.omega ** 2 * (s.M @ g)
+    assert np.abs(r).max() < 1e-9 * np.abs(g).max() * np.abs(s.A).max()
+    # the projection reproduces the gradient exactly
+    e0, _ = system.field_l2(s, g.astype(complex), lambda X: (grad(X).astype(complex), np.zeros((X.shape[0], 1 if dim == 2 else 3))))
+    assert e0 < 1e-10
+
+
+def structural_nnz(mesh):
+    """Number of (row, col) pairs sharing a cell: the sparsity pattern of K."""
+    import scipy.sparse as sp
+    T = mesh.table()
+    nl = T.shape[1]
+    r = np.repeat(T, nl, axis=1).ravel()
+    c = np.tile(T, (1, nl)).ravel()
+    P = sp.coo_matrix((np.ones(r.size), (r, c)), shape=(mesh.n_dofs,) * 2).tocsr()
+    return P.nnz
+
+
+@pytest.mark.parametrize("dim,m,p", [(2, 1, 0), (2, 3, 1), (2, 4, 2), (3, 1, 0), (3, 2, 1), (3, 3, 0)])
+def test_counts_brute_force(dim, m, p):
+    mesh = BoxMesh(dim, (m,) * dim, p=p)
+    assert mesh.n_dofs == expected_counts(dim, m, p)
+    T = mesh.table()
+    pairs = set()
+    for row in T:
+        for a, b in itertools.product(row.tolist(), row.tolist()):
+            pairs.add((a, b))
+    assert structural_nnz(mesh) == len(pairs)
+    s = system.assemble(Problem(dim=dim, n=(m,) * dim + (1,) * (3 - dim), p=p, omega=1.0))
+    assert s.K.nnz <= len(pairs)
+    assert sorted(np.unique(T).tolist()) == list(range(mesh.n_dofs))
+
+
+@pytest.mark.parametrize("dim,m,p,N,nnz", [(2, 16, 0, 544, 3616), (2, 64, 2, 74112, 2286720),
+                                           (2, 128, 1, 131584, 2229248)])
+def test_counts_configs(dim, m, p, N, nnz):
+    mesh = BoxMesh(dim, (m,) * dim, p=p)
+    assert mesh.n_dofs == N and structural_nnz(mesh) == nnz
