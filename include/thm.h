@@ -1,0 +1,195 @@
+/*
+ * thm.h -- C ABI of the MI355X (gfx950) time-harmonic Maxwell solver.
+ *
+ * Method (Beuchler, Kinnewig, Wick, arXiv 2105.11993):
+ *   eq. (1)  curl(mu^{-1} curl E) - w^2 E = 0 in Omega,
+ *            mu^{-1} g^t(curl E) - i k w g^T(E) = 0 on Gamma^inf,
+ *            g^T(E) = g^T(E^inc) on Gamma^inc;
+ *   eqs. (2)-(4) Nedelec discretisation -> real 2x2 block system
+ *            [[K, -C], [C, K]] [E_re; E_im] = [f_re; f_im],  K = A - w^2 M, C = k w M_inf;
+ *   eq. (11) GMRES preconditioned by diag(K, K)^{-1};
+ *   eqs. (5)-(10) impedance-transmission domain decomposition (S = 1).
+ *
+ * Conventions shared by every entry point
+ *   - Meshes are axis-aligned boxes [box_lo, box_hi] split into cells[0] x cells[1]
+ *     (x cells[2]) equal cells; ids are lexicographic with x fastest.
+ *   - Nedelec degree p >= 0 (0 = lowest order), first-kind tensor-product space.
+ *   - DoF vectors are complex128, stored interleaved (re, im) in the global DoF
+ *     order: edge DoFs (x-, y-[, z-]edges), [3D: face DoFs (x-, y-, z-faces)],
+ *     then cell-interior DoFs.  thm_system_info gives the length.
+ *   - Device pointers are HIP device memory on the current device; `stream` is a
+ *     hipStream_t (NULL = default stream).  All work is enqueued on `stream`;
+ *     solves synchronise it before returning so stats are valid.
+ *   - The caller owns every buffer it passes; the library never frees them.
+ *     The library owns everything inside a thm_system until thm_system_destroy.
+ *   - Return value: 0 = OK; > 0 warning with valid output; < 0 error (no output
+ *     guarantee).  The message of the last error on this thread is returned by
+ *     thm_last_error().  No exception or abort crosses this interface.
+ */
+#ifndef THM_H
+#define THM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    THM_OK = 0,
+    THM_NOT_CONVERGED = 1,  /* best iterate written, stats filled */
+    THM_EINVAL = -1,        /* null pointer, bad size, mu <= 0 or non-finite, w <= 0, no Gamma^inf */
+    THM_EUNSUPPORTED = -2,  /* dim not in {2,3}, degree > 3 (2D) / > 2 (3D), uneven partition */
+    THM_ENOMEM = -3,        /* device allocation failed */
+    THM_EHIP = -4,          /* HIP runtime error (message carries hipGetErrorString) */
+    THM_ESINGULAR = -5      /* zero or non-finite pivot while factorising the preconditioner */
+} thm_status;
+
+typedef enum { THM_FP64 = 0, THM_FP32_IR = 1 } thm_precision;
+typedef enum { THM_DDM_GMRES = 0, THM_DDM_JACOBI = 1 } thm_ddm_outer;
+typedef enum { THM_ORTH_CGS = 0, THM_ORTH_CGS2 = 1 } thm_orth;
+
+/* Problem statement (paper Sec. 2, eq. (1); partition eq. (5)).  Copied by thm_assemble. */
+typedef struct {
+    int32_t dim;             /* 2 or 3 */
+    int32_t cells[3];        /* cells per axis (cells[2] ignored in 2D) */
+    double box_lo[3];
+    double box_hi[3];
+    int32_t degree;          /* Nedelec degree p */
+    double omega;            /* w > 0 */
+    double kappa;            /* k > 0, impedance coefficient of eq. (1) */
+    const double *mu;        /* host, n_cells values > 0 (x fastest); NULL -> mu = 1 */
+    uint32_t inc_faces;      /* bit 2*axis+side set -> that side is Gamma^inc; others Gamma^inf */
+    double inc_dir[3];       /* E^inc(x) = pol * exp(-i w dir.x) */
+    double inc_pol_re[3];
+    double inc_pol_im[3];
+    int32_t subdomains[3];   /* box partition for thm_ddm_solve; {1,1,1} = single domain */
+} thm_problem;
+
+/* Solver options.  thm_default_opts fills the defaults listed here. */
+typedef struct {
+    int32_t restart;         /* GMRES restart length m (50) */
+    int32_t max_iter;        /* total inner iterations per solve (5000) */
+    double rtol;             /* stop at ||b - A x|| / ||b|| <= rtol on the real block system (1e-8) */
+    int32_t precision;       /* thm_precision (THM_FP64) */
+    int32_t orth;            /* thm_orth (THM_ORTH_CGS) */
+    int32_t transpose;       /* 1: solve with A^T = [[K, C], [-C, K]] (adjoint) */
+    int32_t ddm_outer;       /* thm_ddm_outer (THM_DDM_GMRES) */
+    double inner_rtol;       /* subdomain solve tolerance inside the DDM (1e-10) */
+    int32_t max_outer;       /* DDM outer iterations / Jacobi sweeps (500) */
+    int32_t outer_restart;   /* restart of the DDM interface GMRES (200) */
+    int32_t batched;         /* 1: all systems/subdomains in one batched launch sequence (1) */
+    int32_t use_graph;       /* 1: replay Arnoldi steps from a captured hipGraph (1) */
+    double ir_inner_rtol;    /* FP32 inner tolerance per refinement step (1e-5) */
+    int32_t max_refine;      /* refinement steps for THM_FP32_IR (30) */
+} thm_solve_opts;
+
+typedef struct {
+    int32_t status;
+    int32_t iters;           /* inner GMRES iterations (max over systems; summed over DDM sweeps) */
+    int32_t outer_iters;     /* DDM outer iterations */
+    int32_t refinements;     /* FP64 refinement steps (THM_FP32_IR) */
+    double rel_residual;     /* final FP64 relative residual of the (glued) solution */
+    double setup_ms;         /* preconditioner factorisation time inside this call */
+    double solve_ms;         /* solve time inside this call */
+} thm_stats;
+
+typedef struct {
+    int64_t n_dofs;          /* complex DoFs (vector length) */
+    int64_t n_free;          /* DoFs not on Gamma^inc */
+    int64_t nnz;             /* stored entries of K (structural pattern) */
+    int64_t nnz_c;           /* stored entries of C */
+    int64_t n_cells;
+    int32_t n_subdomains;
+    int32_t n_layers;        /* block-tridiagonal preconditioner layers */
+    int64_t factor_bytes;    /* FP64 preconditioner storage */
+    int64_t n_interface;     /* complex interface unknowns of the DDM (sum over directed interfaces) */
+} thm_info;
+
+typedef struct thm_system thm_system;
+
+/* Defaults for thm_solve_opts. */
+void thm_default_opts(thm_solve_opts *o);
+
+/*
+ * Assembly (paper eq. (3), (4)).  Builds the DoF map, K = A - w^2 M (batched
+ * element kernel + deterministic gather into CSR), C = k w M_inf, the Dirichlet
+ * values (boundary L2 projection of g^T(E^inc) on Gamma^inc) and the lifted
+ * right-hand side -S_FD g_D.  With subdomains != {1,1,1} it also builds every
+ * subdomain system of eq. (7) and the interface maps of eq. (8).  The
+ * preconditioner of eq. (11) is factorised lazily by the first solve.
+ * Errors: THM_EINVAL, THM_EUNSUPPORTED, THM_ENOMEM, THM_EHIP.
+ */
+thm_status thm_assemble(const thm_problem *p, void *stream, thm_system **out);
+
+/*
+ * Block-preconditioned GMRES on the real 2x2 block form (Sec. 3.2, eq. (11)) for
+ * nsys independent systems; nsys > 1 with opts->batched runs them as one batched
+ * launch sequence.  E_dev[k]: device complex128 of length n_dofs(sys[k]); on
+ * input the initial guess of the free entries (pass zeros), on output the
+ * solution with the Dirichlet entries filled.  stats: host array of nsys.
+ * opts->precision = THM_FP32_IR runs FP32 inner GMRES inside FP64 refinement.
+ * Returns THM_NOT_CONVERGED (best iterate written) if any system misses rtol.
+ */
+thm_status thm_gmres_solve(int32_t nsys, thm_system *const *sys, const thm_solve_opts *opts,
+                           void *const *E_dev, thm_stats *stats, void *stream);
+
+/*
+ * Impedance-transmission domain decomposition (eqs. (5)-(10), S = 1) over the
+ * partition given at assembly, all subdomains resident on this GPU.  Outer
+ * solver: GMRES on (I - A0) g = b (default) or Jacobi sweeps g <- A0 g + b
+ * (with max_outer sweeps and rtol = 0 it returns the iterate after exactly
+ * max_outer sweeps).  Subdomain solves use block-preconditioned GMRES to
+ * opts->inner_rtol.  E_dev: device complex128, global length; output = glued
+ * field (shared DoFs from the lowest subdomain id).
+ */
+thm_status thm_ddm_solve(thm_system *sys, const thm_solve_opts *opts, void *E_dev,
+                         thm_stats *stats, void *stream);
+
+/*
+ * Adjoint gradient of J = int_T |E_h|^2, T = [tgt_lo, tgt_hi] (exact integration
+ * over cell n T), with respect to the per-cell mu:
+ *   dJ/dmu_c = 2 mu_c^{-2} Re(lambda_c^H Ahat_c E_c),  (K - iC)_FF lambda = (M_T E)_F,
+ * lambda computed by one transposed block solve.  E_dev: forward solution
+ * (device complex128, n_dofs).  dJdmu_dev: device double[n_cells].  J_host: J.
+ */
+thm_status thm_adjoint_grad(thm_system *sys, const void *E_dev, const double tgt_lo[3],
+                            const double tgt_hi[3], const thm_solve_opts *opts,
+                            double *dJdmu_dev, double *J_host, void *stream);
+
+/* ---- lifecycle ---------------------------------------------------------- */
+thm_status thm_system_info(const thm_system *sys, thm_info *info);
+/* Replace mu (device double[n_cells]) and re-assemble K in place; the
+ * preconditioner is re-factorised by the next solve. */
+thm_status thm_system_set_mu(thm_system *sys, const double *mu_dev, void *stream);
+void thm_system_destroy(thm_system *sys);
+const char *thm_last_error(void);
+
+/* ---- kernel-level entry points (for parity tests and measurement) -------- */
+/* y = A x (transpose: A^T) on the full DoF vector with Dirichlet rows/columns as
+ * identity; x, y: device complex128[n_dofs].  precision THM_FP32_IR uses the FP32
+ * operator (x, y still complex128). */
+thm_status thm_apply_operator(thm_system *sys, int32_t transpose, int32_t precision,
+                              const void *x_dev, void *y_dev, void *stream);
+/* y = diag(K, K)^{-1} x (eq. (11)), exact factorised inverse; factorises on first use. */
+thm_status thm_apply_precond(thm_system *sys, int32_t precision, const void *x_dev, void *y_dev,
+                             void *stream);
+/* Copy the assembled (not Dirichlet-modified) matrices to host memory.  Arrays
+ * of sizes n_dofs+1 / nnz / nnz / n_dofs+1 / nnz_c / nnz_c; any may be NULL. */
+thm_status thm_export_matrices(thm_system *sys, int32_t *k_rowptr, int32_t *k_col, double *k_val,
+                               int32_t *c_rowptr, int32_t *c_col, double *c_val);
+/* Dirichlet flags (uint8[n_dofs], 1 on Gamma^inc DoFs), the full Dirichlet
+ * vector (complex128[n_dofs], g_D on D else 0) and the lifted right-hand side
+ * (complex128[n_dofs], -S_FD g_D on F else 0), copied to host memory. */
+thm_status thm_export_rhs(thm_system *sys, uint8_t *dir_flags, double *gD, double *rhs);
+/* Element matrices K_c = Ahat_c / mu_c - w^2 Mhat_c of cells [c0, c0+count) (host, row-major). */
+thm_status thm_export_elements(thm_system *sys, int64_t c0, int64_t count, double *out);
+/* Average device time (ms) of `reps` launches of the block SpMV on this system,
+ * measured with HIP events on `stream`; bytes_out: algorithmic bytes per launch. */
+thm_status thm_time_spmv(thm_system *sys, int32_t precision, int32_t reps, double *ms_out,
+                         double *bytes_out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* THM_H */

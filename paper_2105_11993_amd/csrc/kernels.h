@@ -1,0 +1,221 @@
+// Device descriptors and kernel launchers shared by the HIP sources.
+#pragma once
+#include <map>
+
+#include "thm_internal.h"
+
+namespace thm {
+
+constexpr int VCHUNK = 2048;  // scalars per block in Krylov vector kernels
+
+struct MatDesc {
+    int64_t n;
+    const int32_t *rowptr, *col;
+    const void *kval;
+    const int32_t *crowptr, *ccol;
+    const void *cval;
+};
+
+// Flattened block schedule: block b belongs to system s with blkoff[s] <= b < blkoff[s+1].
+struct Sched {
+    DBuf<int32_t> blkoff;
+    std::vector<int32_t> h;
+    int nblocks = 0;
+    void build(const std::vector<int64_t> &units, int64_t per_block, hipStream_t st) {
+        h.assign(units.size() + 1, 0);
+        for (size_t s = 0; s < units.size(); ++s) h[s + 1] = h[s] + (int32_t)((units[s] + per_block - 1) / per_block);
+        nblocks = h.back();
+        blkoff.upload(h, st);
+    }
+};
+
+// A batch of independent systems sharing kernel launches.
+struct Batch {
+    int ns = 0;
+    int maxcols = 64;                  // columns of the partial-sum buffer (>= restart + 2)
+    DBuf<int64_t> off, len, nvec;      // scalar offset, scalar length (2n), complex length n
+    std::vector<int64_t> h_off, h_len, h_nvec;
+    int64_t Ltot = 0;                  // scalars per vector slot
+    Sched vs;                          // VCHUNK scalars per block
+    Sched es;                          // 256 complex entries per block
+    std::map<int, Sched> spmv;         // rows per block = 256 / lpr
+    void init(const std::vector<int64_t> &n, int maxcols_, hipStream_t st) {
+        ns = (int)n.size();
+        maxcols = maxcols_;
+        h_off.assign(ns, 0);
+        h_len.assign(ns, 0);
+        h_nvec = n;
+        int64_t o = 0;
+        for (int s = 0; s < ns; ++s) {
+            h_off[s] = o;
+            h_len[s] = 2 * n[s];
+            o += 2 * n[s];
+            o = (o + 63) & ~int64_t(63);  // 512-byte aligned slots per system
+        }
+        Ltot = o;
+        off.upload(h_off, st);
+        len.upload(h_len, st);
+        nvec.upload(h_nvec, st);
+        vs.build(h_len, VCHUNK, st);
+        es.build(h_nvec, 256, st);
+    }
+    const Sched &spmv_sched(int lpr, hipStream_t st) {
+        auto it = spmv.find(lpr);
+        if (it != spmv.end()) return it->second;
+        Sched &sc = spmv[lpr];
+        sc.build(h_nvec, 256 / lpr, st);
+        return sc;
+    }
+};
+
+// ---- SpMV and Krylov vector kernels (kernels_la.hip)
+template <class T>
+void launch_spmv(int lpr, const MatDesc *mats, const int64_t *off, const Sched &sc, int ns, const int32_t *mask,
+                 const T *x, T *y, const T *b, float csign, hipStream_t st);
+template <class T>
+void launch_dots(const Batch &B, const int32_t *mask, const int32_t *jcnt, const T *V, int64_t ld, const T *w,
+                 double *part, hipStream_t st);
+template <class T>
+void launch_cgs_update(const Batch &B, const int32_t *mask, const int32_t *jcnt, const T *V, int64_t ld, T *w,
+                       const double *h, int ldh, double *part, hipStream_t st);
+template <class T>
+void launch_norm2(const Batch &B, const int32_t *mask, const T *x, double *part, hipStream_t st);
+template <class TI, class TO>
+void launch_scale(const Batch &B, const int32_t *mask, const double *scal, int invert, const TI *x, TO *y1,
+                  const int32_t *jcol, int64_t ld1, TO *y2, hipStream_t st);
+template <class T>
+void launch_lincomb(const Batch &B, const int32_t *mask, const int32_t *kcnt, const T *V, int64_t ld,
+                    const double *coef, int ldc, T *y, hipStream_t st);
+template <class TX, class TZ>
+void launch_axpy(const Batch &B, const int32_t *mask, const double *scal, const TZ *z, TX *x, hipStream_t st);
+void launch_norm_finish(const Batch &B, const double *part, const int32_t *mask, double *out, const double *bnorm,
+                        double rtol, double *resid, int32_t *running, hipStream_t st);
+void launch_reduce_cols(const Batch &B, const int32_t *mask, const int32_t *jcnt, int ncols_fixed,
+                        const double *part, double *out, int ldo, int accumulate, hipStream_t st);
+void launch_cycle_start(const Batch &B, const double *part, int32_t *running, int32_t *active, int32_t *jcnt,
+                        const double *bnorm, double rtol, double *g, int m, double *beta, double *resid,
+                        int32_t *iters, int max_iter, hipStream_t st);
+void launch_arnoldi_finish(const Batch &B, const double *part, int32_t *active, int32_t *jcnt, const double *hcol,
+                           int ldh, double *H, double *cs, double *sn, double *g, double *hnext,
+                           const double *bnorm, double rtol, int m, int32_t *iters, int max_iter, double *est,
+                           hipStream_t st);
+void launch_hsolve(const Batch &B, const int32_t *running, const int32_t *jcnt, const double *H, const double *g,
+                   double *y, int m, hipStream_t st);
+template <class T>
+void launch_zero_flagged(const Batch &B, const uint8_t *const *dirs, T *x, hipStream_t st);
+
+// ---- preconditioner (kernels_prec.hip)
+// Per-system preconditioner description for batched application.
+struct PrecDesc {
+    int64_t n;                 // complex DoFs
+    int64_t n_skel;            // skeleton DoFs
+    int64_t cell_off;          // first interior DoF
+    int32_t n_cells, n_loc, n_int, ne, nlayers;
+    const int32_t *cell_dofs;  // n_cells * n_loc
+    const int32_t *skel_dof, *dof_pos;
+    const int32_t *cond_ptr, *cond_cell, *cond_loc;
+    const int64_t *boff, *sinv_off, *lf_off;
+    const int32_t *bsize;
+    const void *sinv, *lf, *lft;   // double or float
+    const void *kiinv, *F;
+};
+
+struct PrecBatch {
+    int ns = 0, maxlayers = 0;
+    DBuf<PrecDesc> d64, d32;
+    DBuf<int64_t> soff;            // scalar offset of each system's skeleton vector
+    int64_t Stot = 0;              // scalars per skeleton slot
+    Sched skel;                    // 256 skeleton entries per block
+    Sched skel_rows;               // 4 rows (one per wave) per block over all skeleton rows
+    Sched dofs;                    // 256 DoFs per block
+    std::vector<Sched> fwd, bwd;   // per layer step, 4 rows per block
+};
+
+template <class T>
+void launch_prec_apply(const PrecBatch &P, const PrecDesc *d, const int64_t *off, int ns, const int32_t *mask,
+                       const T *r, T *x, T *ws, T *ys, hipStream_t st);
+
+// Setup (FP64): condensation, dense block assembly, block LU with explicit inverses.
+void launch_condense(int ncells, int n_loc, int n_int, const double *Kel, const int32_t *cell_dofs,
+                     const uint8_t *dir, double *kiinv, double *F, double *Kcond, int32_t *status,
+                     hipStream_t st);
+void launch_fill(double *p, int64_t n, double v, hipStream_t st);
+void launch_tgt_gather(int64_t ntgt, const int64_t *tgt_index, const int32_t *tgt_kind, const int32_t *tgt_ptr,
+                       const int32_t *tgt_src, const double *Kcond, double *sinv, double *lf, hipStream_t st);
+void launch_dir_identity(int64_t n_skel, const int32_t *skel_dof, const uint8_t *dir, const int64_t *boff,
+                         const int64_t *sinv_off, const int32_t *bsize, int nlayers, double *sinv, hipStream_t st);
+
+struct GemmDesc {
+    int m, n, k;               // C (m x n) = alpha op(A) op(B) + beta C
+    int ta, tb;                // 1: operand stored transposed
+    const double *A, *B;
+    double *C;
+    int lda, ldb, ldc;
+    double alpha, beta;
+};
+void launch_gemm_batched(const std::vector<GemmDesc> &g, hipStream_t st, DBuf<GemmDesc> &scratch,
+                         Sched &sched);
+
+struct InvDesc {
+    int n;
+    double *A, *W;             // ping-pong buffers (n x n); input in A
+    double *out;               // final inverse (n x n)
+    int32_t *piv;              // n pivot rows
+};
+void launch_invert_batched(const std::vector<InvDesc> &d, int32_t *status, hipStream_t st, DBuf<InvDesc> &scratch);
+void launch_transpose(const double *A, int m, int n, double *At, hipStream_t st);  // At (n x m) = A^T
+void launch_convert(const double *a, float *b, int64_t n, hipStream_t st);
+
+// ---- finite elements (kernels_fe.hip)
+struct FeTables {
+    int npts = 0;
+    DBuf<double> pts, w;         // npts x 3, npts
+    DBuf<double> val, curl;      // n_loc x 3 x npts
+};
+void fe_gauss(int q, DBuf<double> &x, DBuf<double> &w, hipStream_t st);
+void fe_tables_cell(int dim, int p, int q, const LocalFn *fns_dev, int n_loc, FeTables &T, hipStream_t st);
+void fe_tables_side(int dim, int p, int q, int axis, int side, const LocalFn *fns_dev, int n_loc, FeTables &T,
+                    hipStream_t st);
+void launch_element_matrices(int dim, int64_t ncells, int n_loc, const FeTables &T, const double *h,
+                             const double *mu, double omega, double *Kel, hipStream_t st);
+void launch_gather(int64_t nnz, const int32_t *gptr, const int32_t *gsrc, const double *src, double scale,
+                   double *val, hipStream_t st);
+void launch_side_mass(int dim, int nsides, const int32_t *side_axis, const int32_t *side_side,
+                      const int32_t *side_fn, int nf, int n_loc, const FeTables *tabs_dev_host[6],
+                      const double *h, double *out, hipStream_t st);
+void launch_side_load(int dim, int nsides, const int32_t *side_cell, const int32_t *side_axis,
+                      const int32_t *side_side, const int32_t *side_fn, int nf, int n_loc,
+                      const FeTables *tabs[6], const double *h, const double *lo, const int32_t *ncell3,
+                      const double *dirv, const double *pol_re, const double *pol_im, double omega,
+                      double *out, hipStream_t st);
+void launch_gather_vec(int64_t n, const int32_t *ptr, const int32_t *src, const double *vals, double *out,
+                       hipStream_t st);
+void launch_dirichletize(int64_t n, const int32_t *rowptr, const int32_t *col, const uint8_t *dir, double *val,
+                         int diag_one, hipStream_t st);
+void launch_lift_finish(int64_t n, const uint8_t *dir, double *y, hipStream_t st);
+void launch_expand_dirichlet(int64_t n, const uint8_t *dir, const double *gvals, double *x, hipStream_t st);
+void launch_diag_extract(int64_t n, const int32_t *rowptr, const int32_t *col, const double *val, double *d,
+                         hipStream_t st);
+void launch_target_rhs(int dim, int p, int64_t ncells, int n_loc, const LocalFn *fns, const int32_t *cell_dofs,
+                       const double *h, const double *lo, const int32_t *ncell3, const double *tlo,
+                       const double *thi, const double *E, const uint8_t *dir, double *rhs_cells,
+                       double *Jcells, hipStream_t st);
+void launch_cell_gradient(int dim, int64_t ncells, int n_loc, const FeTables &T, const int32_t *cell_dofs,
+                          const double *h, const double *mu, const double *E, const double *lam, double *grad,
+                          hipStream_t st);
+void launch_sum(const double *x, int64_t n, double *out, hipStream_t st);
+
+// ---- domain decomposition and small helpers (kernels_ddm.hip)
+void launch_ddm_rhs(int64_t ntouch, const int32_t *touch_sys, const int32_t *touch_dof, const int32_t *touch_ptr,
+                    const int32_t *touch_src, double *const *rhs, const double *G, hipStream_t st);
+void launch_ddm_update(int64_t nent, const int32_t *ent_sys, const int32_t *ent_row, const int32_t *ent_rev,
+                       const int32_t *ent_mptr, const int32_t *m_col, const double *m_val,
+                       const double *const *X, const double *G, double kw, int mode, double *out, hipStream_t st);
+void launch_ddm_glue(int64_t n, const int32_t *own_sys, const int32_t *own_loc, const double *const *X, double *E,
+                     hipStream_t st);
+void launch_diag_solve(int64_t n, const double *d, const double *r, double *z, hipStream_t st);
+void launch_dot1(int64_t m, const double *a, const double *b, double *out, hipStream_t st);
+void launch_cg_step(int64_t m, int mode, const double *sc, double *x, const double *p, double *r, const double *q,
+                    double *pp, const double *z, hipStream_t st);
+
+}  // namespace thm

@@ -1,0 +1,534 @@
+// Linear-algebra kernels for gfx950: block SpMV on [[K,-C],[C,K]], Krylov vector
+// operations (classical Gram-Schmidt with wave64 reductions, Givens in FP64),
+// dense batched GEMM and Gauss-Jordan inversion (preconditioner setup), and the
+// block-tridiagonal + static-condensation application of diag(K,K)^{-1}.
+//
+// Batching: every kernel serves several independent systems.  A flattened block
+// schedule maps blockIdx.x to (system, block-in-system) so that systems of very
+// different size share one launch without empty blocks.  Vectors of all systems
+// live in one arena; system s owns scalars [off[s], off[s] + 2 n_s) of a slot,
+// stored as interleaved (re, im) pairs.
+#include "kernels.h"
+
+namespace thm {
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ int find_sys(const int32_t *blkoff, int ns, int b) {
+    int lo = 0, hi = ns;  // blkoff[lo] <= b < blkoff[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (blkoff[mid] <= b) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Block reduction of one double over 256 threads (4 waves); result valid in thread 0.
+__device__ __forceinline__ double block_sum256(double v, double *lds) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0) lds[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) r = lds[0] + lds[1] + lds[2] + lds[3];
+    return r;
+}
+
+template <class T> struct V2;
+template <> struct V2<double> { using t = double2; };
+template <> struct V2<float> { using t = float2; };
+
+// ------------------------------------------------------------------ SpMV
+// y = A x  or  y = b - A x, A = [[K, -sC], [sC, K]] acting on interleaved (re, im)
+// pairs, s = +1 (A) or -1 (A^T).  K is read once for both halves.  LPR lanes per row.
+template <int LPR, class T>
+__global__ void __launch_bounds__(256) k_spmv(const MatDesc *__restrict__ mats, const int64_t *__restrict__ off,
+                                              const int32_t *__restrict__ blkoff, int ns,
+                                              const int32_t *__restrict__ mask, const T *__restrict__ xb,
+                                              T *__restrict__ yb, const T *__restrict__ bb, float csign) {
+    using T2 = typename V2<T>::t;
+    const int s = find_sys(blkoff, ns, blockIdx.x);
+    if (mask && !mask[s]) return;
+    const MatDesc m = mats[s];
+    constexpr int RPB = 256 / LPR;
+    const int64_t row = (int64_t)(blockIdx.x - blkoff[s]) * RPB + threadIdx.x / LPR;
+    const int lane = threadIdx.x % LPR;
+    if (row >= m.n) return;
+    const T2 *x = reinterpret_cast<const T2 *>(xb + off[s]);
+    const T *kv = reinterpret_cast<const T *>(m.kval);
+    T ar = 0, ai = 0;
+    const int32_t r0 = m.rowptr[row], r1 = m.rowptr[row + 1];
+    for (int32_t q = r0 + lane; q < r1; q += LPR) {
+        const T k = kv[q];
+        const T2 xv = x[m.col[q]];
+        ar += k * xv.x;
+        ai += k * xv.y;
+    }
+#pragma unroll
+    for (int o = LPR / 2; o > 0; o >>= 1) {
+        ar += __shfl_xor(ar, o, LPR);
+        ai += __shfl_xor(ai, o, LPR);
+    }
+    if (lane == 0) {
+        const T *cv = reinterpret_cast<const T *>(m.cval);
+        const T sg = (T)csign;
+        for (int32_t q = m.crowptr[row]; q < m.crowptr[row + 1]; ++q) {
+            const T c = sg * cv[q];
+            const T2 xv = x[m.ccol[q]];
+            ar -= c * xv.y;
+            ai += c * xv.x;
+        }
+        T2 *y = reinterpret_cast<T2 *>(yb + off[s]);
+        if (bb) {
+            const T2 bv = reinterpret_cast<const T2 *>(bb + off[s])[row];
+            y[row] = T2{bv.x - ar, bv.y - ai};
+        } else {
+            y[row] = T2{ar, ai};
+        }
+    }
+}
+
+template <class T>
+void launch_spmv(int lpr, const MatDesc *mats, const int64_t *off, const Sched &sc, int ns, const int32_t *mask,
+                 const T *x, T *y, const T *b, float csign, hipStream_t st) {
+    if (!sc.nblocks) return;
+    const dim3 g(sc.nblocks), blk(256);
+    switch (lpr) {
+        case 2: k_spmv<2, T><<<g, blk, 0, st>>>(mats, off, sc.blkoff.p, ns, mask, x, y, b, csign); break;
+        case 4: k_spmv<4, T><<<g, blk, 0, st>>>(mats, off, sc.blkoff.p, ns, mask, x, y, b, csign); break;
+        case 8: k_spmv<8, T><<<g, blk, 0, st>>>(mats, off, sc.blkoff.p, ns, mask, x, y, b, csign); break;
+        case 16: k_spmv<16, T><<<g, blk, 0, st>>>(mats, off, sc.blkoff.p, ns, mask, x, y, b, csign); break;
+        case 32: k_spmv<32, T><<<g, blk, 0, st>>>(mats, off, sc.blkoff.p, ns, mask, x, y, b, csign); break;
+        default: k_spmv<64, T><<<g, blk, 0, st>>>(mats, off, sc.blkoff.p, ns, mask, x, y, b, csign); break;
+    }
+    THM_HIP(hipGetLastError());
+}
+template void launch_spmv<double>(int, const MatDesc *, const int64_t *, const Sched &, int, const int32_t *,
+                                  const double *, double *, const double *, float, hipStream_t);
+template void launch_spmv<float>(int, const MatDesc *, const int64_t *, const Sched &, int, const int32_t *,
+                                 const float *, float *, const float *, float, hipStream_t);
+
+// ------------------------------------------------------------------ Krylov vector kernels
+// Vector schedule: each block owns VCHUNK scalars of one system.
+// Multi-dot h_i = <V_i, w>, i = 0..j (j = jcnt[s]); partial sums per block.
+template <class T>
+__global__ void __launch_bounds__(256) k_dots(const int64_t *__restrict__ off, const int64_t *__restrict__ len,
+                                              const int32_t *__restrict__ blkoff, int ns,
+                                              const int32_t *__restrict__ mask, const int32_t *__restrict__ jcnt,
+                                              const T *__restrict__ V, int64_t ld, const T *__restrict__ w,
+                                              double *__restrict__ part, int maxcols) {
+    __shared__ double lds[4];
+    const int s = find_sys(blkoff, ns, blockIdx.x);
+    if (!mask[s]) return;
+    const int j = jcnt[s];
+    const int64_t base = off[s], n = len[s];
+    const int64_t i0 = (int64_t)(blockIdx.x - blkoff[s]) * VCHUNK;
+    T wv[VCHUNK / 256];
+#pragma unroll
+    for (int t = 0; t < VCHUNK / 256; ++t) {
+        const int64_t i = i0 + t * 256 + threadIdx.x;
+        wv[t] = i < n ? w[base + i] : (T)0;
+    }
+    for (int c = 0; c <= j; ++c) {
+        const T *vc = V + (int64_t)c * ld + base;
+        double acc = 0.0;
+#pragma unroll
+        for (int t = 0; t < VCHUNK / 256; ++t) {
+            const int64_t i = i0 + t * 256 + threadIdx.x;
+            if (i < n) acc += (double)vc[i] * (double)wv[t];
+        }
+        acc = block_sum256(acc, lds);
+        if (threadIdx.x == 0) part[(int64_t)blockIdx.x * maxcols + c] = acc;
+    }
+}
+
+// h[s][i] = sum of partials over the blocks of s (one block per system).
+__global__ void k_reduce_cols(const int32_t *__restrict__ blkoff, int ns, const int32_t *__restrict__ mask,
+                              const int32_t *__restrict__ jcnt, int ncols_fixed, const double *__restrict__ part,
+                              int maxcols, double *__restrict__ out, int ldo, int accumulate) {
+    const int s = blockIdx.x;
+    if (s >= ns || (mask && !mask[s])) return;
+    const int nc = ncols_fixed > 0 ? ncols_fixed : jcnt[s] + 1;
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+        double acc = 0.0;
+        for (int b = blkoff[s]; b < blkoff[s + 1]; ++b) acc += part[(int64_t)b * maxcols + c];
+        if (accumulate) out[(int64_t)s * ldo + c] += acc;
+        else out[(int64_t)s * ldo + c] = acc;
+    }
+}
+
+// w -= sum_i V_i h_i (i = 0..j), plus partial ||w||^2 into part[b*maxcols + 0].
+template <class T>
+__global__ void __launch_bounds__(256) k_cgs_update(const int64_t *__restrict__ off, const int64_t *__restrict__ len,
+                                                    const int32_t *__restrict__ blkoff, int ns,
+                                                    const int32_t *__restrict__ mask, const int32_t *__restrict__ jcnt,
+                                                    const T *__restrict__ V, int64_t ld, T *__restrict__ w,
+                                                    const double *__restrict__ h, int ldh, double *__restrict__ part,
+                                                    int maxcols) {
+    __shared__ double lds[4];
+    const int s = find_sys(blkoff, ns, blockIdx.x);
+    if (!mask[s]) return;
+    const int j = jcnt[s];
+    const int64_t base = off[s], n = len[s];
+    const int64_t i0 = (int64_t)(blockIdx.x - blkoff[s]) * VCHUNK;
+    double acc[VCHUNK / 256];
+#pragma unroll
+    for (int t = 0; t < VCHUNK / 256; ++t) {
+        const int64_t i = i0 + t * 256 + threadIdx.x;
+        acc[t] = i < n ? (double)w[base + i] : 0.0;
+    }
+    const double *hs = h + (int64_t)s * ldh;
+    for (int c = 0; c <= j; ++c) {
+        const double hc = hs[c];
+        const T *vc = V + (int64_t)c * ld + base;
+#pragma unroll
+        for (int t = 0; t < VCHUNK / 256; ++t) {
+            const int64_t i = i0 + t * 256 + threadIdx.x;
+            if (i < n) acc[t] -= hc * (double)vc[i];
+        }
+    }
+    double nrm = 0.0;
+#pragma unroll
+    for (int t = 0; t < VCHUNK / 256; ++t) {
+        const int64_t i = i0 + t * 256 + threadIdx.x;
+        if (i < n) {
+            const T v = (T)acc[t];
+            w[base + i] = v;
+            nrm += (double)v * (double)v;
+        }
+    }
+    nrm = block_sum256(nrm, lds);
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * maxcols] = nrm;
+}
+
+// Partial sums of ||x||^2 (and optionally of ||y||^2 into column 1).
+template <class T>
+__global__ void __launch_bounds__(256) k_norm2(const int64_t *__restrict__ off, const int64_t *__restrict__ len,
+                                               const int32_t *__restrict__ blkoff, int ns,
+                                               const int32_t *__restrict__ mask, const T *__restrict__ x,
+                                               double *__restrict__ part, int maxcols) {
+    __shared__ double lds[4];
+    const int s = find_sys(blkoff, ns, blockIdx.x);
+    if (mask && !mask[s]) return;
+    const int64_t base = off[s], n = len[s];
+    const int64_t i0 = (int64_t)(blockIdx.x - blkoff[s]) * VCHUNK;
+    double a = 0.0;
+#pragma unroll
+    for (int t = 0; t < VCHUNK / 256; ++t) {
+        const int64_t i = i0 + t * 256 + threadIdx.x;
+        if (i < n) { const double v = (double)x[base + i]; a += v * v; }
+    }
+    a = block_sum256(a, lds);
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * maxcols] = a;
+}
+
+// y = a_s * x (a_s = scal[s] or 1/scal[s]); optional second destination.
+template <class TI, class TO>
+__global__ void __launch_bounds__(256) k_scale(const int64_t *__restrict__ off, const int64_t *__restrict__ len,
+                                               const int32_t *__restrict__ blkoff, int ns,
+                                               const int32_t *__restrict__ mask, const double *__restrict__ scal,
+                                               int invert, const TI *__restrict__ x, TO *__restrict__ y1,
+                                               const int32_t *__restrict__ jcol, int64_t ld1, TO *__restrict__ y2) {
+    const int s = find_sys(blkoff, ns, blockIdx.x);
+    if (mask && !mask[s]) return;
+    const int64_t base = off[s], n = len[s];
+    const int64_t i0 = (int64_t)(blockIdx.x - blkoff[s]) * VCHUNK;
+    double a = scal ? scal[s] : 1.0;
+    if (invert) a = a != 0.0 ? 1.0 / a : 0.0;
+    TO *d1 = y1 + base + (jcol ? (int64_t)jcol[s] * ld1 : 0);
+#pragma unroll
+    for (int t = 0; t < VCHUNK / 256; ++t) {
+        const int64_t i = i0 + t * 256 + threadIdx.x;
+        if (i < n) {
+            const TO v = (TO)(a * (double)x[base + i]);
+            d1[i] = v;
+            if (y2) y2[base + i] = v;
+        }
+    }
+}
+
+// y (+)= sum_{c<k} V_c coef[s][c]  (k = kcnt[s]); used for the GMRES solution update.
+template <class T>
+__global__ void __launch_bounds__(256) k_lincomb(const int64_t *__restrict__ off, const int64_t *__restrict__ len,
+                                                 const int32_t *__restrict__ blkoff, int ns,
+                                                 const int32_t *__restrict__ mask, const int32_t *__restrict__ kcnt,
+                                                 const T *__restrict__ V, int64_t ld, const double *__restrict__ coef,
+                                                 int ldc, T *__restrict__ y) {
+    const int s = find_sys(blkoff, ns, blockIdx.x);
+    if (mask && !mask[s]) return;
+    const int k = kcnt[s];
+    const int64_t base = off[s], n = len[s];
+    const int64_t i0 = (int64_t)(blockIdx.x - blkoff[s]) * VCHUNK;
+    double acc[VCHUNK / 256];
+#pragma unroll
+    for (int t = 0; t < VCHUNK / 256; ++t) acc[t] = 0.0;
+    for (int c = 0; c < k; ++c) {
+        const double a = coef[(int64_t)s * ldc + c];
+        const T *vc = V + (int64_t)c * ld + base;
+#pragma unroll
+        for (int t = 0; t < VCHUNK / 256; ++t) {
+            const int64_t i = i0 + t * 256 + threadIdx.x;
+            if (i < n) acc[t] += a * (double)vc[i];
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < VCHUNK / 256; ++t) {
+        const int64_t i = i0 + t * 256 + threadIdx.x;
+        if (i < n) y[base + i] = (T)acc[t];
+    }
+}
+
+// x += a_s * z (a_s = scal ? scal[s] : 1), x in TX, z in TZ.
+template <class TX, class TZ>
+__global__ void __launch_bounds__(256) k_axpy(const int64_t *__restrict__ off, const int64_t *__restrict__ len,
+                                              const int32_t *__restrict__ blkoff, int ns,
+                                              const int32_t *__restrict__ mask, const double *__restrict__ scal,
+                                              const TZ *__restrict__ z, TX *__restrict__ x) {
+    const int s = find_sys(blkoff, ns, blockIdx.x);
+    if (mask && !mask[s]) return;
+    const int64_t base = off[s], n = len[s];
+    const int64_t i0 = (int64_t)(blockIdx.x - blkoff[s]) * VCHUNK;
+    const double a = scal ? scal[s] : 1.0;
+#pragma unroll
+    for (int t = 0; t < VCHUNK / 256; ++t) {
+        const int64_t i = i0 + t * 256 + threadIdx.x;
+        if (i < n) x[base + i] = (TX)((double)x[base + i] + a * (double)z[base + i]);
+    }
+}
+
+// Start of a GMRES cycle: beta = ||r||; running systems whose beta/bnorm <= rtol stop.
+// Initialises g = (beta, 0, ...), jcnt = 0, active flag, and 1/beta for v_0.
+__global__ void k_cycle_start(int ns, const int32_t *__restrict__ blkoff, const double *__restrict__ part,
+                              int maxcols, int32_t *__restrict__ running, int32_t *__restrict__ active,
+                              int32_t *__restrict__ jcnt, const double *__restrict__ bnorm, double rtol,
+                              double *__restrict__ g, int m, double *__restrict__ beta_out,
+                              double *__restrict__ resid_out, int32_t *__restrict__ iters, int max_iter) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= ns) return;
+    if (!running[s]) { active[s] = 0; return; }
+    double b2 = 0.0;
+    for (int b = blkoff[s]; b < blkoff[s + 1]; ++b) b2 += part[(int64_t)b * maxcols];
+    const double beta = sqrt(b2);
+    const double rel = bnorm[s] > 0.0 ? beta / bnorm[s] : 0.0;
+    resid_out[s] = rel;
+    beta_out[s] = beta;
+    jcnt[s] = 0;
+    if (!(rel > rtol) || iters[s] >= max_iter || !isfinite(rel)) {
+        running[s] = 0;
+        active[s] = 0;
+        return;
+    }
+    active[s] = 1;
+    double *gs = g + (int64_t)s * (m + 1);
+    gs[0] = beta;
+    for (int i = 1; i <= m; ++i) gs[i] = 0.0;
+}
+
+// After the dots/update of Arnoldi step j: finish column j of H (FP64), apply the
+// previous Givens rotations, build the new one, update g and the residual estimate.
+__global__ void k_arnoldi_finish(int ns, const int32_t *__restrict__ blkoff, const double *__restrict__ part,
+                                 int maxcols, int32_t *__restrict__ active, int32_t *__restrict__ jcnt,
+                                 const double *__restrict__ hcol, int ldh, double *__restrict__ H,
+                                 double *__restrict__ cs, double *__restrict__ sn, double *__restrict__ g,
+                                 double *__restrict__ hnext, const double *__restrict__ bnorm, double rtol, int m,
+                                 int32_t *__restrict__ iters, int max_iter, double *__restrict__ resid_est) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= ns || !active[s]) return;
+    const int j = jcnt[s];
+    double w2 = 0.0;
+    for (int b = blkoff[s]; b < blkoff[s + 1]; ++b) w2 += part[(int64_t)b * maxcols];
+    const double hn = sqrt(w2);
+    double *Hs = H + (int64_t)s * (m + 1) * m;  // column-major (m+1) x m
+    double *col = Hs + (int64_t)j * (m + 1);
+    const double *hc = hcol + (int64_t)s * ldh;
+    for (int i = 0; i <= j; ++i) col[i] = hc[i];
+    double *css = cs + (int64_t)s * m, *sns = sn + (int64_t)s * m, *gs = g + (int64_t)s * (m + 1);
+    for (int i = 0; i < j; ++i) {
+        const double t = css[i] * col[i] + sns[i] * col[i + 1];
+        col[i + 1] = -sns[i] * col[i] + css[i] * col[i + 1];
+        col[i] = t;
+    }
+    const double a = col[j], b = hn;
+    const double den = hypot(a, b);
+    double c = 1.0, sv = 0.0, r = a;
+    if (den > 0.0) { c = a / den; sv = b / den; r = den; }
+    css[j] = c;
+    sns[j] = sv;
+    col[j] = r;
+    col[j + 1] = 0.0;
+    gs[j + 1] = -sv * gs[j];
+    gs[j] = c * gs[j];
+    hnext[s] = hn;
+    jcnt[s] = j + 1;
+    iters[s] += 1;
+    const double est = fabs(gs[j + 1]) / bnorm[s];
+    resid_est[s] = est;
+    const bool breakdown = !(hn > 1e-300) || !(den > 0.0);
+    if (est <= rtol || breakdown || j + 1 >= m || iters[s] >= max_iter || !isfinite(est)) active[s] = 0;
+}
+
+// y = H^{-1} g on the first k = jcnt[s] columns (upper triangular after Givens).
+__global__ void k_hsolve(int ns, const int32_t *__restrict__ running, const int32_t *__restrict__ jcnt,
+                         const double *__restrict__ H, const double *__restrict__ g, double *__restrict__ y, int m) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= ns || !running[s]) return;
+    const int k = jcnt[s];
+    const double *Hs = H + (int64_t)s * (m + 1) * m;
+    const double *gs = g + (int64_t)s * (m + 1);
+    double *ys = y + (int64_t)s * (m + 1);
+    for (int i = k - 1; i >= 0; --i) {
+        double acc = gs[i];
+        for (int c = i + 1; c < k; ++c) acc -= Hs[(int64_t)c * (m + 1) + i] * ys[c];
+        const double d = Hs[(int64_t)i * (m + 1) + i];
+        ys[i] = d != 0.0 ? acc / d : 0.0;
+    }
+}
+
+// Zero the entries flagged in `dir` (Dirichlet rows) of a complex vector.
+template <class T>
+__global__ void k_zero_flagged(const int64_t *__restrict__ off, const int64_t *__restrict__ nvec,
+                               const int32_t *__restrict__ blkoff, int ns, const uint8_t *const *__restrict__ dirs,
+                               T *__restrict__ x) {
+    const int s = find_sys(blkoff, ns, blockIdx.x);
+    const int64_t i = (int64_t)(blockIdx.x - blkoff[s]) * 256 + threadIdx.x;
+    if (i >= nvec[s]) return;
+    if (dirs[s][i]) { x[off[s] + 2 * i] = (T)0; x[off[s] + 2 * i + 1] = (T)0; }
+}
+
+// out[s] = sqrt(sum of partials); with check: resid[s] = out/bnorm, running[s] = 0 if <= rtol.
+__global__ void k_norm_finish(int ns, const int32_t *__restrict__ blkoff, const double *__restrict__ part,
+                              int maxcols, const int32_t *__restrict__ mask, double *__restrict__ out,
+                              const double *__restrict__ bnorm, double rtol, double *__restrict__ resid,
+                              int32_t *__restrict__ running) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= ns || (mask && !mask[s])) return;
+    double a = 0.0;
+    for (int b = blkoff[s]; b < blkoff[s + 1]; ++b) a += part[(int64_t)b * maxcols];
+    const double nrm = sqrt(a);
+    out[s] = nrm;
+    if (bnorm) {
+        const double rel = bnorm[s] > 0.0 ? nrm / bnorm[s] : 0.0;
+        resid[s] = rel;
+        if (running && !(rel > rtol)) running[s] = 0;
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+#define VGRID(sc) dim3((sc).nblocks), dim3(256), 0, st
+#define VGUARD(B) if (!(B).vs.nblocks) return
+
+template <class T>
+void launch_dots(const Batch &B, const int32_t *mask, const int32_t *jcnt, const T *V, int64_t ld, const T *w,
+                 double *part, hipStream_t st) {
+    VGUARD(B);
+    k_dots<T><<<VGRID(B.vs)>>>(B.off.p, B.len.p, B.vs.blkoff.p, B.ns, mask, jcnt, V, ld, w, part, B.maxcols);
+    THM_HIP(hipGetLastError());
+}
+template <class T>
+void launch_cgs_update(const Batch &B, const int32_t *mask, const int32_t *jcnt, const T *V, int64_t ld, T *w,
+                       const double *h, int ldh, double *part, hipStream_t st) {
+    VGUARD(B);
+    k_cgs_update<T><<<VGRID(B.vs)>>>(B.off.p, B.len.p, B.vs.blkoff.p, B.ns, mask, jcnt, V, ld, w, h, ldh, part,
+                                     B.maxcols);
+    THM_HIP(hipGetLastError());
+}
+template <class T>
+void launch_norm2(const Batch &B, const int32_t *mask, const T *x, double *part, hipStream_t st) {
+    VGUARD(B);
+    k_norm2<T><<<VGRID(B.vs)>>>(B.off.p, B.len.p, B.vs.blkoff.p, B.ns, mask, x, part, B.maxcols);
+    THM_HIP(hipGetLastError());
+}
+template <class TI, class TO>
+void launch_scale(const Batch &B, const int32_t *mask, const double *scal, int invert, const TI *x, TO *y1,
+                  const int32_t *jcol, int64_t ld1, TO *y2, hipStream_t st) {
+    VGUARD(B);
+    k_scale<TI, TO><<<VGRID(B.vs)>>>(B.off.p, B.len.p, B.vs.blkoff.p, B.ns, mask, scal, invert, x, y1, jcol, ld1, y2);
+    THM_HIP(hipGetLastError());
+}
+template <class T>
+void launch_lincomb(const Batch &B, const int32_t *mask, const int32_t *kcnt, const T *V, int64_t ld,
+                    const double *coef, int ldc, T *y, hipStream_t st) {
+    VGUARD(B);
+    k_lincomb<T><<<VGRID(B.vs)>>>(B.off.p, B.len.p, B.vs.blkoff.p, B.ns, mask, kcnt, V, ld, coef, ldc, y);
+    THM_HIP(hipGetLastError());
+}
+template <class TX, class TZ>
+void launch_axpy(const Batch &B, const int32_t *mask, const double *scal, const TZ *z, TX *x, hipStream_t st) {
+    VGUARD(B);
+    k_axpy<TX, TZ><<<VGRID(B.vs)>>>(B.off.p, B.len.p, B.vs.blkoff.p, B.ns, mask, scal, z, x);
+    THM_HIP(hipGetLastError());
+}
+void launch_norm_finish(const Batch &B, const double *part, const int32_t *mask, double *out, const double *bnorm,
+                        double rtol, double *resid, int32_t *running, hipStream_t st) {
+    k_norm_finish<<<(B.ns + 63) / 64, 64, 0, st>>>(B.ns, B.vs.blkoff.p, part, B.maxcols, mask, out, bnorm, rtol,
+                                                   resid, running);
+    THM_HIP(hipGetLastError());
+}
+void launch_reduce_cols(const Batch &B, const int32_t *mask, const int32_t *jcnt, int ncols_fixed,
+                        const double *part, double *out, int ldo, int accumulate, hipStream_t st) {
+    k_reduce_cols<<<B.ns, 64, 0, st>>>(B.vs.blkoff.p, B.ns, mask, jcnt, ncols_fixed, part, B.maxcols, out, ldo,
+                                       accumulate);
+    THM_HIP(hipGetLastError());
+}
+void launch_cycle_start(const Batch &B, const double *part, int32_t *running, int32_t *active, int32_t *jcnt,
+                        const double *bnorm, double rtol, double *g, int m, double *beta, double *resid,
+                        int32_t *iters, int max_iter, hipStream_t st) {
+    k_cycle_start<<<(B.ns + 63) / 64, 64, 0, st>>>(B.ns, B.vs.blkoff.p, part, B.maxcols, running, active, jcnt,
+                                                   bnorm, rtol, g, m, beta, resid, iters, max_iter);
+    THM_HIP(hipGetLastError());
+}
+void launch_arnoldi_finish(const Batch &B, const double *part, int32_t *active, int32_t *jcnt, const double *hcol,
+                           int ldh, double *H, double *cs, double *sn, double *g, double *hnext,
+                           const double *bnorm, double rtol, int m, int32_t *iters, int max_iter, double *est,
+                           hipStream_t st) {
+    k_arnoldi_finish<<<(B.ns + 63) / 64, 64, 0, st>>>(B.ns, B.vs.blkoff.p, part, B.maxcols, active, jcnt, hcol,
+                                                      ldh, H, cs, sn, g, hnext, bnorm, rtol, m, iters, max_iter,
+                                                      est);
+    THM_HIP(hipGetLastError());
+}
+void launch_hsolve(const Batch &B, const int32_t *running, const int32_t *jcnt, const double *H, const double *g,
+                   double *y, int m, hipStream_t st) {
+    k_hsolve<<<(B.ns + 63) / 64, 64, 0, st>>>(B.ns, running, jcnt, H, g, y, m);
+    THM_HIP(hipGetLastError());
+}
+template <class T>
+void launch_zero_flagged(const Batch &B, const uint8_t *const *dirs, T *x, hipStream_t st) {
+    if (!B.es.nblocks) return;
+    k_zero_flagged<T><<<B.es.nblocks, 256, 0, st>>>(B.off.p, B.nvec.p, B.es.blkoff.p, B.ns, dirs, x);
+    THM_HIP(hipGetLastError());
+}
+
+#define INST_T(T)                                                                                            \
+    template void launch_dots<T>(const Batch &, const int32_t *, const int32_t *, const T *, int64_t,         \
+                                 const T *, double *, hipStream_t);                                          \
+    template void launch_cgs_update<T>(const Batch &, const int32_t *, const int32_t *, const T *, int64_t,   \
+                                       T *, const double *, int, double *, hipStream_t);                     \
+    template void launch_norm2<T>(const Batch &, const int32_t *, const T *, double *, hipStream_t);          \
+    template void launch_lincomb<T>(const Batch &, const int32_t *, const int32_t *, const T *, int64_t,      \
+                                    const double *, int, T *, hipStream_t);                                  \
+    template void launch_zero_flagged<T>(const Batch &, const uint8_t *const *, T *, hipStream_t);
+INST_T(double)
+INST_T(float)
+template void launch_scale<double, double>(const Batch &, const int32_t *, const double *, int, const double *,
+                                           double *, const int32_t *, int64_t, double *, hipStream_t);
+template void launch_scale<float, float>(const Batch &, const int32_t *, const double *, int, const float *,
+                                         float *, const int32_t *, int64_t, float *, hipStream_t);
+template void launch_scale<float, double>(const Batch &, const int32_t *, const double *, int, const float *,
+                                          double *, const int32_t *, int64_t, double *, hipStream_t);
+template void launch_scale<double, float>(const Batch &, const int32_t *, const double *, int, const double *,
+                                          float *, const int32_t *, int64_t, float *, hipStream_t);
+template void launch_axpy<double, double>(const Batch &, const int32_t *, const double *, const double *, double *,
+                                          hipStream_t);
+template void launch_axpy<float, float>(const Batch &, const int32_t *, const double *, const float *, float *,
+                                        hipStream_t);
+template void launch_axpy<double, float>(const Batch &, const int32_t *, const double *, const float *, double *,
+                                         hipStream_t);
+
+}  // namespace thm

@@ -1,0 +1,553 @@
+// Block preconditioner diag(K, K)^{-1} of eq. (11) with an exact factorised K^{-1}:
+//  1. static condensation of the cell-interior DoFs (per-cell dense inverse),
+//  2. block-tridiagonal LU over layers of skeleton (edge/face) DoFs stacked along
+//     the last axis, with explicitly inverted pivot blocks S_k^{-1} and the
+//     couplings Lf_k = B_k S_{k-1}^{-1} (and Lf_k^T) stored densely.
+// Application to the two right-hand sides (real and imaginary halves) is a chain
+// of dense GEMVs (one launch per layer step, batched over systems).
+#include "kernels.h"
+
+namespace thm {
+
+__device__ __forceinline__ int find_sys2(const int32_t *blkoff, int ns, int b) {
+    int lo = 0, hi = ns;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (blkoff[mid] <= b) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+template <class T> struct P2;
+template <> struct P2<double> { using t = double2; };
+template <> struct P2<float> { using t = float2; };
+
+// ------------------------------------------------------------------ condensation (setup)
+// One block per cell: K'_c = K_c with Dirichlet rows/columns zeroed; Kii^{-1} by
+// Gauss-Jordan with partial pivoting; F = K'_ei Kii^{-1}; Kcond = K'_ee - F K'_ie.
+__global__ void __launch_bounds__(256) k_condense(int n_loc, int n_int, const double *__restrict__ Kel,
+                                                  const int32_t *__restrict__ cell_dofs,
+                                                  const uint8_t *__restrict__ dir, double *__restrict__ kiinv,
+                                                  double *__restrict__ Fout, double *__restrict__ Kcond,
+                                                  int32_t *status) {
+    __shared__ double Kc[64 * 64];
+    __shared__ double Ai[32 * 32];
+    __shared__ double prow[32], fcol[32];
+    __shared__ int perm[32], pivs[32];
+    __shared__ uint8_t dl[64];
+    const int64_t c = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int ne = n_loc - n_int;
+    for (int u = tid; u < n_loc; u += blockDim.x) dl[u] = dir[cell_dofs[c * n_loc + u]];
+    __syncthreads();
+    for (int id = tid; id < n_loc * n_loc; id += blockDim.x) {
+        const int u = id / n_loc, v = id % n_loc;
+        Kc[id] = (dl[u] || dl[v]) ? 0.0 : Kel[c * n_loc * n_loc + id];
+    }
+    __syncthreads();
+    if (n_int > 0) {
+        for (int id = tid; id < n_int * n_int; id += blockDim.x) {
+            const int i = id / n_int, j = id % n_int;
+            Ai[id] = Kc[(ne + i) * n_loc + ne + j];
+        }
+        __syncthreads();
+        for (int col = 0; col < n_int; ++col) {
+            if (tid == 0) {
+                int p = col;
+                double best = fabs(Ai[col * n_int + col]);
+                for (int i = col + 1; i < n_int; ++i) {
+                    const double v = fabs(Ai[i * n_int + col]);
+                    if (v > best) { best = v; p = i; }
+                }
+                pivs[col] = p;
+                if (!(best > 0.0) || !isfinite(best)) atomicOr(status, 1);
+            }
+            __syncthreads();
+            const int p = pivs[col];
+            if (p != col)
+                for (int j = tid; j < n_int; j += blockDim.x) {
+                    const double t = Ai[col * n_int + j];
+                    Ai[col * n_int + j] = Ai[p * n_int + j];
+                    Ai[p * n_int + j] = t;
+                }
+            __syncthreads();
+            const double pv = Ai[col * n_int + col];
+            const double ipv = pv != 0.0 ? 1.0 / pv : 0.0;
+            for (int j = tid; j < n_int; j += blockDim.x) {
+                prow[j] = (j == col) ? ipv : Ai[col * n_int + j] * ipv;
+                fcol[j] = Ai[j * n_int + col];
+            }
+            __syncthreads();
+            for (int id = tid; id < n_int * n_int; id += blockDim.x) {
+                const int i = id / n_int, j = id % n_int;
+                if (i == col) Ai[id] = prow[j];
+                else Ai[id] = (j == col ? 0.0 : Ai[id]) - fcol[i] * prow[j];
+            }
+            __syncthreads();
+        }
+        // undo the row interchanges as column swaps in reverse order
+        if (tid == 0) {
+            for (int j = 0; j < n_int; ++j) perm[j] = j;
+            for (int col = n_int - 1; col >= 0; --col) {
+                const int p = pivs[col];
+                const int t = perm[col];
+                perm[col] = perm[p];
+                perm[p] = t;
+            }
+        }
+        __syncthreads();
+        for (int id = tid; id < n_int * n_int; id += blockDim.x) {
+            const int i = id / n_int, j = id % n_int;
+            kiinv[c * n_int * n_int + id] = Ai[i * n_int + perm[j]];
+        }
+        __syncthreads();
+        for (int id = tid; id < n_int * n_int; id += blockDim.x) Ai[id] = kiinv[c * n_int * n_int + id];
+        __syncthreads();
+        // F = K'_ei Kii^{-1} (ne x n_int)
+        for (int id = tid; id < ne * n_int; id += blockDim.x) {
+            const int u = id / n_int, m = id % n_int;
+            double acc = 0.0;
+            for (int k = 0; k < n_int; ++k) acc += Kc[u * n_loc + ne + k] * Ai[k * n_int + m];
+            Fout[c * ne * n_int + id] = acc;
+        }
+        __syncthreads();
+    }
+    for (int id = tid; id < ne * ne; id += blockDim.x) {
+        const int u = id / ne, v = id % ne;
+        double acc = Kc[u * n_loc + v];
+        for (int m = 0; m < n_int; ++m) acc -= Fout[c * ne * n_int + u * n_int + m] * Kc[(ne + m) * n_loc + v];
+        Kcond[c * ne * ne + id] = acc;
+    }
+}
+
+void launch_condense(int ncells, int n_loc, int n_int, const double *Kel, const int32_t *cell_dofs,
+                     const uint8_t *dir, double *kiinv, double *F, double *Kcond, int32_t *status, hipStream_t st) {
+    if (n_loc > 64 || n_int > 32) fail(THM_EUNSUPPORTED, "condensation supports n_loc <= 64 and n_int <= 32");
+    k_condense<<<ncells, 256, 0, st>>>(n_loc, n_int, Kel, cell_dofs, dir, kiinv, F, Kcond, status);
+    THM_HIP(hipGetLastError());
+}
+
+__global__ void k_fill(double *p, int64_t n, double v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+void launch_fill(double *p, int64_t n, double v, hipStream_t st) {
+    if (!n) return;
+    k_fill<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(p, n, v);
+    THM_HIP(hipGetLastError());
+}
+
+__global__ void k_tgt_gather(int64_t ntgt, const int64_t *tgt_index, const int32_t *tgt_kind, const int32_t *tgt_ptr,
+                             const int32_t *tgt_src, const double *Kcond, double *sinv, double *lf) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntgt) return;
+    double acc = 0.0;
+    for (int32_t e = tgt_ptr[t]; e < tgt_ptr[t + 1]; ++e) acc += Kcond[tgt_src[e]];
+    (tgt_kind[t] ? lf : sinv)[tgt_index[t]] = acc;
+}
+void launch_tgt_gather(int64_t ntgt, const int64_t *tgt_index, const int32_t *tgt_kind, const int32_t *tgt_ptr,
+                       const int32_t *tgt_src, const double *Kcond, double *sinv, double *lf, hipStream_t st) {
+    if (!ntgt) return;
+    k_tgt_gather<<<(unsigned)((ntgt + 255) / 256), 256, 0, st>>>(ntgt, tgt_index, tgt_kind, tgt_ptr, tgt_src, Kcond,
+                                                                 sinv, lf);
+    THM_HIP(hipGetLastError());
+}
+
+__global__ void k_dir_identity(int64_t n_skel, const int32_t *skel_dof, const uint8_t *dir, const int64_t *boff,
+                               const int64_t *sinv_off, const int32_t *bsize, int nlayers, double *sinv) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_skel || !dir[skel_dof[t]]) return;
+    int lo = 0, hi = nlayers;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (boff[mid] <= t) lo = mid; else hi = mid;
+    }
+    const int64_t i = t - boff[lo];
+    sinv[sinv_off[lo] + i * bsize[lo] + i] = 1.0;
+}
+void launch_dir_identity(int64_t n_skel, const int32_t *skel_dof, const uint8_t *dir, const int64_t *boff,
+                         const int64_t *sinv_off, const int32_t *bsize, int nlayers, double *sinv, hipStream_t st) {
+    k_dir_identity<<<(unsigned)((n_skel + 255) / 256), 256, 0, st>>>(n_skel, skel_dof, dir, boff, sinv_off, bsize,
+                                                                     nlayers, sinv);
+    THM_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ batched FP64 GEMM (setup)
+// 64x64 tiles, 16-deep K steps staged through LDS, 4x4 outputs per thread.
+__global__ void __launch_bounds__(256) k_gemm(const GemmDesc *__restrict__ ds, const int32_t *__restrict__ blkoff,
+                                              int nd) {
+    __shared__ double As[16][65];
+    __shared__ double Bs[16][65];
+    const int di = find_sys2(blkoff, nd, blockIdx.x);
+    const GemmDesc d = ds[di];
+    const int tiles_n = (d.n + 63) / 64;
+    const int tile = blockIdx.x - blkoff[di];
+    const int tm = tile / tiles_n, tn = tile % tiles_n;
+    const int row0 = tm * 64, col0 = tn * 64;
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    double acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+    for (int k0 = 0; k0 < d.k; k0 += 16) {
+        for (int e = threadIdx.x; e < 1024; e += 256) {
+            const int r = e / 16, kk = e % 16;  // A tile: 64 rows x 16 k
+            const int gi = row0 + r, gk = k0 + kk;
+            double v = 0.0;
+            if (gi < d.m && gk < d.k) v = d.ta ? d.A[(int64_t)gk * d.lda + gi] : d.A[(int64_t)gi * d.lda + gk];
+            As[kk][r] = v;
+            const int kb = e / 64, cb = e % 64;  // B tile: 16 k x 64 cols
+            const int gk2 = k0 + kb, gj = col0 + cb;
+            double w = 0.0;
+            if (gk2 < d.k && gj < d.n) w = d.tb ? d.B[(int64_t)gj * d.ldb + gk2] : d.B[(int64_t)gk2 * d.ldb + gj];
+            Bs[kb][cb] = w;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            double a[4], b[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) { a[q] = As[kk][ty * 4 + q]; b[q] = Bs[kk][tx * 4 + q]; }
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[p][q] = fma(a[p], b[q], acc[p][q]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const int gi = row0 + ty * 4 + p;
+        if (gi >= d.m) continue;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int gj = col0 + tx * 4 + q;
+            if (gj >= d.n) continue;
+            double *cp = d.C + (int64_t)gi * d.ldc + gj;
+            *cp = d.alpha * acc[p][q] + (d.beta != 0.0 ? d.beta * *cp : 0.0);
+        }
+    }
+}
+
+void launch_gemm_batched(const std::vector<GemmDesc> &g, hipStream_t st, DBuf<GemmDesc> &scratch, Sched &sched) {
+    if (g.empty()) return;
+    std::vector<int64_t> tiles(g.size());
+    for (size_t i = 0; i < g.size(); ++i) tiles[i] = (int64_t)((g[i].m + 63) / 64) * ((g[i].n + 63) / 64);
+    sched.build(tiles, 1, st);
+    scratch.upload(g, st);
+    if (sched.nblocks == 0) return;
+    k_gemm<<<sched.nblocks, 256, 0, st>>>(scratch.p, sched.blkoff.p, (int)g.size());
+    THM_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ batched Gauss-Jordan inversion
+__global__ void k_gj_pivot(const InvDesc *ds, int nd, int col, int parity, int32_t *status) {
+    __shared__ double bv[256];
+    __shared__ int bi[256];
+    const int di = blockIdx.x;
+    if (di >= nd) return;
+    const InvDesc d = ds[di];
+    if (col >= d.n) return;
+    const double *A = parity ? d.W : d.A;
+    double best = -1.0;
+    int bidx = col;
+    for (int i = col + threadIdx.x; i < d.n; i += blockDim.x) {
+        const double v = fabs(A[(int64_t)i * d.n + col]);
+        if (v > best) { best = v; bidx = i; }
+    }
+    bv[threadIdx.x] = best;
+    bi[threadIdx.x] = bidx;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            const double v2 = bv[threadIdx.x + o];
+            const int i2 = bi[threadIdx.x + o];
+            if (v2 > bv[threadIdx.x] || (v2 == bv[threadIdx.x] && i2 < bi[threadIdx.x])) {
+                bv[threadIdx.x] = v2;
+                bi[threadIdx.x] = i2;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        d.piv[col] = bi[0];
+        if (!(bv[0] > 0.0) || !isfinite(bv[0])) atomicOr(status, 1);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_gj_update(const InvDesc *__restrict__ ds, const int32_t *__restrict__ blkoff,
+                                                   int nd, int col, int parity) {
+    const int di = find_sys2(blkoff, nd, blockIdx.x);
+    const InvDesc d = ds[di];
+    const int n = d.n;
+    if (col >= n) return;
+    const int64_t id = (int64_t)(blockIdx.x - blkoff[di]) * 256 + threadIdx.x;
+    if (id >= (int64_t)n * n) return;
+    const double *Ain = parity ? d.W : d.A;
+    double *Aout = parity ? d.A : d.W;
+    const int i = (int)(id / n), j = (int)(id % n);
+    const int p = d.piv[col];
+    const double pv = Ain[(int64_t)p * n + col];
+    const double ipv = pv != 0.0 ? 1.0 / pv : 0.0;
+    const double pr = (j == col) ? ipv : Ain[(int64_t)p * n + j] * ipv;
+    double out;
+    if (i == col) {
+        out = pr;
+    } else {
+        const int src = (i == p) ? col : i;
+        const double f = Ain[(int64_t)src * n + col];
+        const double e = (j == col) ? 0.0 : Ain[(int64_t)src * n + j];
+        out = e - f * pr;
+    }
+    Aout[id] = out;
+}
+
+__global__ void k_gj_perm_build(const InvDesc *ds, int nd) {
+    const int di = blockIdx.x * blockDim.x + threadIdx.x;
+    if (di >= nd) return;
+    const InvDesc d = ds[di];
+    int32_t *perm = d.piv + d.n;
+    for (int j = 0; j < d.n; ++j) perm[j] = j;
+    for (int c = d.n - 1; c >= 0; --c) {
+        const int p = d.piv[c];
+        const int32_t t = perm[c];
+        perm[c] = perm[p];
+        perm[p] = t;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_gj_perm_apply(const InvDesc *__restrict__ ds,
+                                                       const int32_t *__restrict__ blkoff, int nd) {
+    const int di = find_sys2(blkoff, nd, blockIdx.x);
+    const InvDesc d = ds[di];
+    const int n = d.n;
+    const int64_t id = (int64_t)(blockIdx.x - blkoff[di]) * 256 + threadIdx.x;
+    if (id >= (int64_t)n * n) return;
+    const double *res = (n % 2 == 0) ? d.A : d.W;
+    const int i = (int)(id / n), j = (int)(id % n);
+    d.out[id] = res[(int64_t)i * n + d.piv[n + j]];
+}
+
+void launch_invert_batched(const std::vector<InvDesc> &d, int32_t *status, hipStream_t st, DBuf<InvDesc> &scratch) {
+    if (d.empty()) return;
+    int nmax = 0;
+    std::vector<int64_t> elems(d.size());
+    for (size_t i = 0; i < d.size(); ++i) {
+        nmax = std::max(nmax, d[i].n);
+        elems[i] = (int64_t)d[i].n * d[i].n;
+    }
+    Sched sc;
+    sc.build(elems, 256, st);
+    scratch.upload(d, st);
+    const int nd = (int)d.size();
+    for (int col = 0; col < nmax; ++col) {
+        const int parity = col & 1;
+        k_gj_pivot<<<nd, 256, 0, st>>>(scratch.p, nd, col, parity, status);
+        k_gj_update<<<sc.nblocks, 256, 0, st>>>(scratch.p, sc.blkoff.p, nd, col, parity);
+    }
+    k_gj_perm_build<<<(nd + 63) / 64, 64, 0, st>>>(scratch.p, nd);
+    k_gj_perm_apply<<<sc.nblocks, 256, 0, st>>>(scratch.p, sc.blkoff.p, nd);
+    THM_HIP(hipGetLastError());
+    THM_HIP(hipStreamSynchronize(st));  // keeps the schedule alive until the kernels finished
+}
+
+__global__ void k_transpose(const double *A, int m, int n, double *At) {
+    __shared__ double t[32][33];
+    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;  // 32 x 8 threads
+    for (int r = ty; r < 32; r += 8) {
+        const int i = by + r, j = bx + tx;
+        if (i < m && j < n) t[r][tx] = A[(int64_t)i * n + j];
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int j = bx + r, i = by + tx;
+        if (i < m && j < n) At[(int64_t)j * m + i] = t[tx][r];
+    }
+}
+void launch_transpose(const double *A, int m, int n, double *At, hipStream_t st) {
+    if (!m || !n) return;
+    dim3 g((n + 31) / 32, (m + 31) / 32);
+    k_transpose<<<g, 256, 0, st>>>(A, m, n, At);
+    THM_HIP(hipGetLastError());
+}
+
+__global__ void k_convert(const double *a, float *b, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (float)a[i];
+}
+void launch_convert(const double *a, float *b, int64_t n, hipStream_t st) {
+    if (!n) return;
+    k_convert<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(a, b, n);
+    THM_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ application (batched)
+// ws[t] = r[skel_dof[t]] - sum over cells c of t of (F_c r_int(c))[local t]
+template <class T>
+__global__ void __launch_bounds__(256) k_cond_fwd(const PrecDesc *__restrict__ pd, const int64_t *__restrict__ off,
+                                                  const int64_t *__restrict__ soff, const int32_t *__restrict__ blkoff,
+                                                  int ns, const int32_t *__restrict__ mask, const T *__restrict__ rb,
+                                                  T *__restrict__ wsb) {
+    using T2 = typename P2<T>::t;
+    const int s = find_sys2(blkoff, ns, blockIdx.x);
+    if (mask && !mask[s]) return;
+    const PrecDesc d = pd[s];
+    const int64_t t = (int64_t)(blockIdx.x - blkoff[s]) * 256 + threadIdx.x;
+    if (t >= d.n_skel) return;
+    const T2 *r = reinterpret_cast<const T2 *>(rb + off[s]);
+    T2 *ws = reinterpret_cast<T2 *>(wsb + soff[s]);
+    const T *F = reinterpret_cast<const T *>(d.F);
+    T2 acc = r[d.skel_dof[t]];
+    for (int32_t e = d.cond_ptr[t]; e < d.cond_ptr[t + 1]; ++e) {
+        const int64_t c = d.cond_cell[e];
+        const int le = d.cond_loc[e];
+        const T *f = F + (c * d.ne + le) * d.n_int;
+        const T2 *ri = r + d.cell_off + c * d.n_int;
+        for (int m = 0; m < d.n_int; ++m) {
+            const T fv = f[m];
+            const T2 rv = ri[m];
+            acc.x -= fv * rv.x;
+            acc.y -= fv * rv.y;
+        }
+    }
+    ws[t] = acc;
+}
+
+// Wave-per-row GEMV on layer blocks.  MODE 0: forward step k (ws_k -= Lf_k ws_{k-1});
+// MODE 1: ys = blockdiag(S^{-1}) ws over all layers; MODE 2: backward step k
+// (ys_k -= Lf_{k+1}^T ys_{k+1}).
+template <class T, int MODE>
+__global__ void __launch_bounds__(256) k_layer_gemv(const PrecDesc *__restrict__ pd, const int64_t *__restrict__ soff,
+                                                    const int32_t *__restrict__ blkoff, int ns,
+                                                    const int32_t *__restrict__ mask, int k, T *__restrict__ wsb,
+                                                    T *__restrict__ ysb) {
+    using T2 = typename P2<T>::t;
+    const int s = find_sys2(blkoff, ns, blockIdx.x);
+    if (mask && !mask[s]) return;
+    const PrecDesc d = pd[s];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t row = (int64_t)(blockIdx.x - blkoff[s]) * 4 + wave;
+    T2 *ws = reinterpret_cast<T2 *>(wsb + soff[s]);
+    T2 *ys = reinterpret_cast<T2 *>(ysb + soff[s]);
+    const T *M;
+    const T2 *x;
+    T2 *y;
+    int64_t ncols, rows;
+    if (MODE == 0) {
+        rows = d.bsize[k];
+        if (row >= rows) return;
+        ncols = d.bsize[k - 1];
+        M = reinterpret_cast<const T *>(d.lf) + d.lf_off[k] + row * ncols;
+        x = ws + d.boff[k - 1];
+        y = ws + d.boff[k] + row;
+    } else if (MODE == 1) {
+        if (row >= d.n_skel) return;
+        int lo = 0, hi = d.nlayers;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (d.boff[mid] <= row) lo = mid; else hi = mid;
+        }
+        const int64_t i = row - d.boff[lo];
+        ncols = d.bsize[lo];
+        M = reinterpret_cast<const T *>(d.sinv) + d.sinv_off[lo] + i * ncols;
+        x = ws + d.boff[lo];
+        y = ys + row;
+    } else {
+        rows = d.bsize[k];
+        if (row >= rows) return;
+        ncols = d.bsize[k + 1];
+        // Lf_{k+1}^T is b_k x b_{k+1}, stored at the same offset as Lf_{k+1}
+        M = reinterpret_cast<const T *>(d.lft) + d.lf_off[k + 1] + row * ncols;
+        x = ys + d.boff[k + 1];
+        y = ys + d.boff[k] + row;
+    }
+    T ar = 0, ai = 0;
+    for (int64_t j = lane; j < ncols; j += 64) {
+        const T a = M[j];
+        const T2 xv = x[j];
+        ar += a * xv.x;
+        ai += a * xv.y;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        ar += __shfl_xor(ar, o, 64);
+        ai += __shfl_xor(ai, o, 64);
+    }
+    if (lane == 0) {
+        if (MODE == 1) {
+            *y = T2{ar, ai};
+        } else {
+            T2 v = *y;
+            v.x -= ar;
+            v.y -= ai;
+            *y = v;
+        }
+    }
+}
+
+// x[g] = ys[pos(g)] on skeleton DoFs; interiors: x_i = Kii^{-1} r_i - F^T x_e.
+template <class T>
+__global__ void __launch_bounds__(256) k_cond_bwd(const PrecDesc *__restrict__ pd, const int64_t *__restrict__ off,
+                                                  const int64_t *__restrict__ soff, const int32_t *__restrict__ blkoff,
+                                                  int ns, const int32_t *__restrict__ mask, const T *__restrict__ rb,
+                                                  const T *__restrict__ ysb, T *__restrict__ xb) {
+    using T2 = typename P2<T>::t;
+    const int s = find_sys2(blkoff, ns, blockIdx.x);
+    if (mask && !mask[s]) return;
+    const PrecDesc d = pd[s];
+    const int64_t g = (int64_t)(blockIdx.x - blkoff[s]) * 256 + threadIdx.x;
+    if (g >= d.n) return;
+    const T2 *ys = reinterpret_cast<const T2 *>(ysb + soff[s]);
+    T2 *x = reinterpret_cast<T2 *>(xb + off[s]);
+    if (g < d.cell_off) {
+        x[g] = ys[d.dof_pos[g]];
+        return;
+    }
+    const T2 *r = reinterpret_cast<const T2 *>(rb + off[s]);
+    const int64_t c = (g - d.cell_off) / d.n_int;
+    const int m = (int)((g - d.cell_off) % d.n_int);
+    const T *Ki = reinterpret_cast<const T *>(d.kiinv) + (c * d.n_int + m) * d.n_int;
+    const T2 *ri = r + d.cell_off + c * d.n_int;
+    T2 acc{0, 0};
+    for (int q = 0; q < d.n_int; ++q) {
+        acc.x += Ki[q] * ri[q].x;
+        acc.y += Ki[q] * ri[q].y;
+    }
+    const T *F = reinterpret_cast<const T *>(d.F) + c * d.ne * d.n_int;
+    const int32_t *cd = d.cell_dofs + c * d.n_loc;
+    for (int le = 0; le < d.ne; ++le) {
+        const T f = F[le * d.n_int + m];
+        const T2 xe = ys[d.dof_pos[cd[le]]];
+        acc.x -= f * xe.x;
+        acc.y -= f * xe.y;
+    }
+    x[g] = acc;
+}
+
+template <class T>
+void launch_prec_apply(const PrecBatch &P, const PrecDesc *d, const int64_t *off, int ns, const int32_t *mask,
+                       const T *r, T *x, T *ws, T *ys, hipStream_t st) {
+    if (P.skel.nblocks)
+        k_cond_fwd<T><<<P.skel.nblocks, 256, 0, st>>>(d, off, P.soff.p, P.skel.blkoff.p, ns, mask, r, ws);
+    for (int k = 1; k < P.maxlayers; ++k)
+        if (P.fwd[k].nblocks)
+            k_layer_gemv<T, 0><<<P.fwd[k].nblocks, 256, 0, st>>>(d, P.soff.p, P.fwd[k].blkoff.p, ns, mask, k, ws, ys);
+    if (P.skel_rows.nblocks)
+        k_layer_gemv<T, 1><<<P.skel_rows.nblocks, 256, 0, st>>>(d, P.soff.p, P.skel_rows.blkoff.p, ns, mask, 0, ws,
+                                                               ys);
+    for (int k = P.maxlayers - 2; k >= 0; --k)
+        if (P.bwd[k].nblocks)
+            k_layer_gemv<T, 2><<<P.bwd[k].nblocks, 256, 0, st>>>(d, P.soff.p, P.bwd[k].blkoff.p, ns, mask, k, ws, ys);
+    if (P.dofs.nblocks)
+        k_cond_bwd<T><<<P.dofs.nblocks, 256, 0, st>>>(d, off, P.soff.p, P.dofs.blkoff.p, ns, mask, r, ys, x);
+    THM_HIP(hipGetLastError());
+}
+
+template void launch_prec_apply<double>(const PrecBatch &, const PrecDesc *, const int64_t *, int, const int32_t *,
+                                        const double *, double *, double *, double *, hipStream_t);
+template void launch_prec_apply<float>(const PrecBatch &, const PrecDesc *, const int64_t *, int, const int32_t *,
+                                       const float *, float *, float *, float *, hipStream_t);
+
+}  // namespace thm

@@ -1,0 +1,134 @@
+// Internal solver structures: the assembled system, the batched GMRES workspace and
+// the per-call batched solve context.
+#pragma once
+#include <functional>
+
+#include "kernels.h"
+
+namespace thm {
+struct Ddm;
+}
+
+// One assembled problem (global or one subdomain).  Owns all device memory.
+struct thm_system {
+    thm_problem prob{};
+    std::vector<double> mu_host;
+    uint32_t iface_sides = 0;  // sides that are DDM interfaces (impedance with k w)
+    thm::Topo topo;
+    thm::HostCSR K, C, Minc;
+    std::vector<thm::Side> sides_c, sides_inc;  // sides carrying C; Gamma^inc sides
+    std::vector<uint8_t> dir;
+    thm::Layering L;
+    int64_t n = 0, n_free = 0;
+    int nf = 0;  // local functions per side
+
+    thm::DBuf<thm::LocalFn> fns;
+    thm::FeTables tcell, tside, tload;
+    thm::DBuf<int32_t> cell_dofs, k_rowptr, k_col, k_gptr, k_gsrc, c_rowptr, c_col, c_gptr, c_gsrc;
+    thm::DBuf<int32_t> side_fn, sc_axis, sc_side, sc_cell, si_axis, si_side, si_cell;
+    thm::DBuf<double> h, lo;
+    thm::DBuf<int32_t> ncell;
+    thm::DBuf<double> mu_d;
+    thm::DBuf<double> kel, kraw, kval, craw, cval;
+    thm::DBuf<float> kval32, cval32;
+    thm::DBuf<uint8_t> dir_d;
+    thm::DBuf<double> gD, rhs;  // complex, full length (2n doubles)
+    thm::DBuf<int32_t> d2c_ptr, d2c_src;
+
+    // preconditioner (exact factorised K^{-1}, FP64 and FP32 copies)
+    bool prec_ready = false;
+    thm::DBuf<int32_t> Lskel_dof, Ldof_pos, Lcond_ptr, Lcond_cell, Lcond_loc, Lbsize;
+    thm::DBuf<int64_t> Lboff, Lsinv_off, Llf_off;
+    thm::DBuf<double> sinv, lf, lft, kiinv, F;
+    thm::DBuf<float> sinv32, lf32, lft32, kiinv32, F32;
+    double prec_setup_ms = 0.0;
+
+    // domain decomposition
+    std::vector<std::unique_ptr<thm_system>> subs;
+    std::unique_ptr<thm::Ddm> ddm;
+
+    ~thm_system();
+};
+
+namespace thm {
+
+struct Krylov {
+    Batch B;
+    int m = 50;
+    DBuf<double> H, cs, sn, g, y, hcol, hcol2, hnext, bnorm, beta, resid, est, part;
+    DBuf<int32_t> running, active, jcnt, iters;
+    DBuf<double> V64, w64, z64, cur64;
+    DBuf<float> V32, w32, z32, cur32;
+    int32_t *pinned = nullptr;  // 2 x ns host flags
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    struct GraphSlot {
+        hipGraphExec_t exec = nullptr;
+        hipGraph_t graph = nullptr;
+        int key_T = -1, orth = -1, max_iter = -1;
+        float csign = 0.f;
+        double rtol = -1.0;
+        const void *owner = nullptr;
+    } slots[4];
+    void init(const std::vector<int64_t> &n, int m, hipStream_t st);
+    template <class T> T *V();
+    template <class T> T *w();
+    template <class T> T *z();
+    template <class T> T *cur();
+    template <class T> void ensure(hipStream_t st);
+    void drop_graphs();
+    ~Krylov();
+};
+
+template <class T>
+struct KOps {
+    // y = A x (b == nullptr) or y = b - A x, for systems with mask set
+    std::function<void(const T *x, T *y, const T *b, const int32_t *mask)> apply;
+    // y = P^{-1} x
+    std::function<void(const T *x, T *y, const int32_t *mask)> prec;
+    bool graphable = false;
+    const void *owner = nullptr;  // identity of the operator (graph cache key)
+    float csign = 1.f;
+};
+
+struct GmresParams {
+    double rtol = 1e-8;
+    int max_iter = 5000;
+    int orth = THM_ORTH_CGS;
+    bool use_graph = true;
+};
+
+template <class T>
+void gmres_run(Krylov &K, const KOps<T> &ops, const T *b, T *x, const int32_t *mask_in, const GmresParams &p,
+               hipStream_t st);
+
+// Batched solve context over assembled (sub)systems.
+struct Ctx {
+    std::vector<thm_system *> sys;
+    int ns = 0;
+    hipStream_t st = nullptr;
+    Krylov K;
+    PrecBatch P;
+    DBuf<MatDesc> mat64, mat32;
+    DBuf<const uint8_t *> dirs;
+    DBuf<double> x64, b64, r64, ws64, ys64;
+    DBuf<float> x32, b32, ws32, ys32;
+    DBuf<int32_t> mask_all, run_ir;
+    DBuf<double> rnorm, bnorm64, resid64;
+    int lpr64 = 8, lpr32 = 8;
+
+    void build(const std::vector<thm_system *> &s, int m, hipStream_t stream);
+    KOps<double> ops64(float csign);
+    KOps<float> ops32(float csign);
+    // Solve A x = b for the systems in mask (device, nullable = all); b64/x64 slots hold
+    // the right-hand sides and initial guesses (zero on Dirichlet rows).
+    void solve(const thm_solve_opts &o, float csign, const int32_t *mask, std::vector<int> &iters,
+               std::vector<int> &refines, std::vector<double> &resid);
+    void autotune();
+    void copy_in(int s, const double *src_dev, double *slot);
+    void copy_out(int s, const double *slot, double *dst_dev);
+};
+
+void setup_precond(const std::vector<thm_system *> &systems, hipStream_t st);
+double now_ms();
+
+}  // namespace thm
