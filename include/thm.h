@@ -48,6 +48,12 @@ typedef enum {
 typedef enum { THM_FP64 = 0, THM_FP32_IR = 1 } thm_precision;
 typedef enum { THM_DDM_GMRES = 0, THM_DDM_JACOBI = 1 } thm_ddm_outer;
 typedef enum { THM_ORTH_CGS = 0, THM_ORTH_CGS2 = 1 } thm_orth;
+/* Scalars of the Arnoldi process on the real block vectors: THM_KRYLOV_REAL is the
+ * GMRES of the 2N real block system of eq. (4) taken literally (real Hessenberg);
+ * THM_KRYLOV_COMPLEX uses complex scalars (inner products <v, w> = sum conj(v) w on
+ * the interleaved (re, im) pairs), i.e. the Krylov space is closed under
+ * multiplication by i.  Operator, preconditioner and solution are the same. */
+typedef enum { THM_KRYLOV_COMPLEX = 0, THM_KRYLOV_REAL = 1 } thm_krylov;
 
 /* Problem statement (paper Sec. 2, eq. (1); partition eq. (5)).  Copied by thm_assemble. */
 typedef struct {
@@ -80,8 +86,9 @@ typedef struct {
     int32_t outer_restart;   /* restart of the DDM interface GMRES (200) */
     int32_t batched;         /* 1: all systems/subdomains in one batched launch sequence (1) */
     int32_t use_graph;       /* 1: replay Arnoldi steps from a captured hipGraph (1) */
-    double ir_inner_rtol;    /* FP32 inner tolerance per refinement step (1e-5) */
+    double ir_inner_rtol;    /* floor of the FP32 inner tolerance per refinement step (1e-6) */
     int32_t max_refine;      /* refinement steps for THM_FP32_IR (30) */
+    int32_t krylov;          /* thm_krylov (THM_KRYLOV_COMPLEX) */
 } thm_solve_opts;
 
 typedef struct {

@@ -20,6 +20,7 @@ THM_OK, THM_NOT_CONVERGED = 0, 1
 THM_FP64, THM_FP32_IR = 0, 1
 THM_DDM_GMRES, THM_DDM_JACOBI = 0, 1
 THM_ORTH_CGS, THM_ORTH_CGS2 = 0, 1
+THM_KRYLOV_COMPLEX, THM_KRYLOV_REAL = 0, 1
 
 _d3 = ctypes.c_double * 3
 _i3 = ctypes.c_int32 * 3
@@ -37,7 +38,7 @@ class ThmSolveOpts(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("orth", ctypes.c_int32), ("transpose", ctypes.c_int32),
                 ("ddm_outer", ctypes.c_int32), ("inner_rtol", ctypes.c_double), ("max_outer", ctypes.c_int32),
                 ("outer_restart", ctypes.c_int32), ("batched", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("ir_inner_rtol", ctypes.c_double), ("max_refine", ctypes.c_int32)]
+                ("ir_inner_rtol", ctypes.c_double), ("max_refine", ctypes.c_int32), ("krylov", ctypes.c_int32)]
 
 
 class ThmStats(ctypes.Structure):

@@ -6,7 +6,8 @@
 
 namespace thm {
 
-constexpr int VCHUNK = 2048;  // scalars per block in Krylov vector kernels
+constexpr int VCHUNK = 4096;  // scalars per block in Krylov vector kernels (even)
+constexpr int NPW = 4;        // partial-sum slots per block (one per wave)
 
 struct MatDesc {
     int64_t n;
@@ -32,7 +33,7 @@ struct Sched {
 // A batch of independent systems sharing kernel launches.
 struct Batch {
     int ns = 0;
-    int maxcols = 64;                  // columns of the partial-sum buffer (>= restart + 2)
+    int maxcols = 64;                  // columns of the partial-sum buffer (>= 2 (restart + 1))
     DBuf<int64_t> off, len, nvec;      // scalar offset, scalar length (2n), complex length n
     std::vector<int64_t> h_off, h_len, h_nvec;
     int64_t Ltot = 0;                  // scalars per vector slot
@@ -74,7 +75,7 @@ void launch_spmv(int lpr, const MatDesc *mats, const int64_t *off, const Sched &
                  const T *x, T *y, const T *b, float csign, hipStream_t st);
 template <class T>
 void launch_dots(const Batch &B, const int32_t *mask, const int32_t *jcnt, const T *V, int64_t ld, const T *w,
-                 double *part, hipStream_t st);
+                 double *part, int cplx, hipStream_t st);
 template <class T>
 void launch_cgs_update(const Batch &B, const int32_t *mask, const int32_t *jcnt, const T *V, int64_t ld, T *w,
                        const double *h, int ldh, double *part, hipStream_t st);
@@ -97,8 +98,8 @@ void launch_cycle_start(const Batch &B, const double *part, int32_t *running, in
                         int32_t *iters, int max_iter, hipStream_t st);
 void launch_arnoldi_finish(const Batch &B, const double *part, int32_t *active, int32_t *jcnt, const double *hcol,
                            int ldh, double *H, double *cs, double *sn, double *g, double *hnext,
-                           const double *bnorm, double rtol, int m, int32_t *iters, int max_iter, double *est,
-                           hipStream_t st);
+                           const double *bnorm, const double *rtol_d, int m, int32_t *iters, int max_iter,
+                           double *est, hipStream_t st);
 void launch_hsolve(const Batch &B, const int32_t *running, const int32_t *jcnt, const double *H, const double *g,
                    double *y, int m, hipStream_t st);
 template <class T>
@@ -114,21 +115,39 @@ struct PrecDesc {
     const int32_t *cell_dofs;  // n_cells * n_loc
     const int32_t *skel_dof, *dof_pos;
     const int32_t *cond_ptr, *cond_cell, *cond_loc;
-    const int64_t *boff, *sinv_off, *lf_off;
-    const int32_t *bsize;
-    const void *sinv, *lf, *lft;   // double or float
-    const void *kiinv, *F;
+    const void *kiinv, *F;         // double or float
+};
+
+// One multi-GEMV task of the cyclic-reduction application (see kernels_prec.hip).
+constexpr int SEGMAX = 16;  // input segments of one task (the dense last block reads all its positions)
+struct BcrTask {
+    const void *M;             // row-major rows x cols (double or float)
+    int32_t rows, cols, nseg, group;
+    int32_t seg_len[SEGMAX], seg_src[SEGMAX];  // seg_src: 0 = ws (reduced RHS), 1 = ys (solution)
+    int64_t seg_off[SEGMAX];   // complex offset of the segment inside a member's skeleton vector
+    int64_t out_off;           // complex offset of the output block
+    int32_t out_dst, subtract;
+    int32_t nmc;               // member chunks of the group (blocks per row block)
+};
+
+constexpr int BCR_RB = 8;                            // rows per block of the cyclic-reduction GEMV
+inline int bcr_mc(int prec) { return prec ? 4 : 2; }  // members per block (FP32, FP64)
+
+struct PrecPhase {
+    DBuf<BcrTask> tasks[2];    // FP64, FP32 matrices
+    Sched sched[2];            // blocks = row blocks x member chunks
+    int ntasks = 0;
 };
 
 struct PrecBatch {
-    int ns = 0, maxlayers = 0;
+    int ns = 0;
     DBuf<PrecDesc> d64, d32;
     DBuf<int64_t> soff;            // scalar offset of each system's skeleton vector
     int64_t Stot = 0;              // scalars per skeleton slot
     Sched skel;                    // 256 skeleton entries per block
-    Sched skel_rows;               // 4 rows (one per wave) per block over all skeleton rows
     Sched dofs;                    // 256 DoFs per block
-    std::vector<Sched> fwd, bwd;   // per layer step, 4 rows per block
+    DBuf<int32_t> memb_ptr, memb;  // factor group -> member systems
+    std::vector<PrecPhase> phases; // forward levels, top, backward levels
 };
 
 template <class T>
@@ -159,11 +178,14 @@ void launch_gemm_batched(const std::vector<GemmDesc> &g, hipStream_t st, DBuf<Ge
 struct InvDesc {
     int n;
     double *A, *W;             // ping-pong buffers (n x n); input in A
-    double *out;               // final inverse (n x n)
-    int32_t *piv;              // n pivot rows
+    double *out;               // final inverse (n x n, leading dimension ldo)
+    int32_t *piv;              // 2n: pivot rows, then the column permutation
+    int ldo;
 };
 void launch_invert_batched(const std::vector<InvDesc> &d, int32_t *status, hipStream_t st, DBuf<InvDesc> &scratch);
-void launch_transpose(const double *A, int m, int n, double *At, hipStream_t st);  // At (n x m) = A^T
+// At (n x m, leading dimension ldt) = alpha * A^T, A (m x n, leading dimension lda)
+void launch_transpose(const double *A, int m, int n, int lda, double *At, int ldt, double alpha, hipStream_t st);
+void launch_compare(const void *a, const void *b, int64_t n8, int32_t *mismatch, hipStream_t st);
 void launch_convert(const double *a, float *b, int64_t n, hipStream_t st);
 
 // ---- finite elements (kernels_fe.hip)

@@ -116,55 +116,83 @@ template void launch_spmv<float>(int, const MatDesc *, const int64_t *, const Sc
                                  const float *, float *, const float *, float, hipStream_t);
 
 // ------------------------------------------------------------------ Krylov vector kernels
-// Vector schedule: each block owns VCHUNK scalars of one system.
-// Multi-dot h_i = <V_i, w>, i = 0..j (j = jcnt[s]); partial sums per block.
+// Vectors are interleaved (re, im) pairs.  With cplx = 1 the Arnoldi process uses
+// complex scalars (h = <v, w> = sum conj(v) w; the Krylov space is invariant under
+// multiplication by i, i.e. the complex GMRES of K + iC expressed on the real block
+// vectors); with cplx = 0 it is the real GMRES of the 2N real block system (the
+// imaginary part of every inner product is dropped).  Hessenberg, Givens and the
+// least-squares solve are FP64 (complex storage in both modes).
+// Each block owns VCHUNK scalars of one system and writes one partial per wave.
+constexpr int PPT = VCHUNK / 512;  // complex pairs per thread
+
+template <class T>
+__device__ __forceinline__ void wave_store(double v, double *dst) {
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) *dst = v;
+}
+
 template <class T>
 __global__ void __launch_bounds__(256) k_dots(const int64_t *__restrict__ off, const int64_t *__restrict__ len,
                                               const int32_t *__restrict__ blkoff, int ns,
                                               const int32_t *__restrict__ mask, const int32_t *__restrict__ jcnt,
                                               const T *__restrict__ V, int64_t ld, const T *__restrict__ w,
-                                              double *__restrict__ part, int maxcols) {
-    __shared__ double lds[4];
+                                              double *__restrict__ part, int maxcols, int cplx) {
+    using T2 = typename V2<T>::t;
     const int s = find_sys(blkoff, ns, blockIdx.x);
     if (!mask[s]) return;
     const int j = jcnt[s];
-    const int64_t base = off[s], n = len[s];
-    const int64_t i0 = (int64_t)(blockIdx.x - blkoff[s]) * VCHUNK;
-    T wv[VCHUNK / 256];
+    const int64_t base = off[s], np = len[s] / 2;
+    const int64_t p0 = (int64_t)(blockIdx.x - blkoff[s]) * (VCHUNK / 2);
+    const int wave = threadIdx.x >> 6;
+    double *pp = part + ((int64_t)blockIdx.x * NPW + wave) * maxcols;
+    T2 wv[PPT];
+    const T2 *wp = reinterpret_cast<const T2 *>(w + base);
 #pragma unroll
-    for (int t = 0; t < VCHUNK / 256; ++t) {
-        const int64_t i = i0 + t * 256 + threadIdx.x;
-        wv[t] = i < n ? w[base + i] : (T)0;
+    for (int t = 0; t < PPT; ++t) {
+        const int64_t i = p0 + t * 256 + threadIdx.x;
+        wv[t] = i < np ? wp[i] : T2{0, 0};
     }
     for (int c = 0; c <= j; ++c) {
-        const T *vc = V + (int64_t)c * ld + base;
-        double acc = 0.0;
+        const T2 *vc = reinterpret_cast<const T2 *>(V + (int64_t)c * ld + base);
+        double ar = 0.0, ai = 0.0;
 #pragma unroll
-        for (int t = 0; t < VCHUNK / 256; ++t) {
-            const int64_t i = i0 + t * 256 + threadIdx.x;
-            if (i < n) acc += (double)vc[i] * (double)wv[t];
+        for (int t = 0; t < PPT; ++t) {
+            const int64_t i = p0 + t * 256 + threadIdx.x;
+            if (i < np) {
+                const T2 v = vc[i];
+                ar += (double)v.x * (double)wv[t].x + (double)v.y * (double)wv[t].y;
+                ai += (double)v.x * (double)wv[t].y - (double)v.y * (double)wv[t].x;
+            }
         }
-        acc = block_sum256(acc, lds);
-        if (threadIdx.x == 0) part[(int64_t)blockIdx.x * maxcols + c] = acc;
+        wave_store<T>(ar, pp + 2 * c);
+        wave_store<T>(cplx ? ai : 0.0, pp + 2 * c + 1);
     }
 }
 
-// h[s][i] = sum of partials over the blocks of s (one block per system).
+// out[s][k] (k < ncols) = sum of the partial slots of system s.  Grid (systems,
+// column chunks of 16); each wave reduces 4 columns, lanes striding over the slots.
 __global__ void k_reduce_cols(const int32_t *__restrict__ blkoff, int ns, const int32_t *__restrict__ mask,
                               const int32_t *__restrict__ jcnt, int ncols_fixed, const double *__restrict__ part,
                               int maxcols, double *__restrict__ out, int ldo, int accumulate) {
     const int s = blockIdx.x;
     if (s >= ns || (mask && !mask[s])) return;
-    const int nc = ncols_fixed > 0 ? ncols_fixed : jcnt[s] + 1;
-    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+    const int nc = ncols_fixed > 0 ? ncols_fixed : 2 * (jcnt[s] + 1);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int b0 = blkoff[s] * NPW, b1 = blkoff[s + 1] * NPW;
+    for (int k = 0; k < 4; ++k) {
+        const int c = blockIdx.y * 16 + wave * 4 + k;
+        if (c >= nc) break;
         double acc = 0.0;
-        for (int b = blkoff[s]; b < blkoff[s + 1]; ++b) acc += part[(int64_t)b * maxcols + c];
-        if (accumulate) out[(int64_t)s * ldo + c] += acc;
-        else out[(int64_t)s * ldo + c] = acc;
+        for (int b = b0 + lane; b < b1; b += 64) acc += part[(int64_t)b * maxcols + c];
+        acc = wave_sum(acc);
+        if (lane == 0) {
+            if (accumulate) out[(int64_t)s * ldo + c] += acc;
+            else out[(int64_t)s * ldo + c] = acc;
+        }
     }
 }
 
-// w -= sum_i V_i h_i (i = 0..j), plus partial ||w||^2 into part[b*maxcols + 0].
+// w -= sum_c V_c h_c (complex h), plus per-wave partial ||w||^2 in column 0.
 template <class T>
 __global__ void __launch_bounds__(256) k_cgs_update(const int64_t *__restrict__ off, const int64_t *__restrict__ len,
                                                     const int32_t *__restrict__ blkoff, int ns,
@@ -172,49 +200,54 @@ __global__ void __launch_bounds__(256) k_cgs_update(const int64_t *__restrict__ 
                                                     const T *__restrict__ V, int64_t ld, T *__restrict__ w,
                                                     const double *__restrict__ h, int ldh, double *__restrict__ part,
                                                     int maxcols) {
-    __shared__ double lds[4];
+    using T2 = typename V2<T>::t;
     const int s = find_sys(blkoff, ns, blockIdx.x);
     if (!mask[s]) return;
     const int j = jcnt[s];
-    const int64_t base = off[s], n = len[s];
-    const int64_t i0 = (int64_t)(blockIdx.x - blkoff[s]) * VCHUNK;
-    double acc[VCHUNK / 256];
+    const int64_t base = off[s], np = len[s] / 2;
+    const int64_t p0 = (int64_t)(blockIdx.x - blkoff[s]) * (VCHUNK / 2);
+    T2 *wp = reinterpret_cast<T2 *>(w + base);
+    double xr[PPT], xi[PPT];
 #pragma unroll
-    for (int t = 0; t < VCHUNK / 256; ++t) {
-        const int64_t i = i0 + t * 256 + threadIdx.x;
-        acc[t] = i < n ? (double)w[base + i] : 0.0;
+    for (int t = 0; t < PPT; ++t) {
+        const int64_t i = p0 + t * 256 + threadIdx.x;
+        const T2 v = i < np ? wp[i] : T2{0, 0};
+        xr[t] = v.x;
+        xi[t] = v.y;
     }
     const double *hs = h + (int64_t)s * ldh;
     for (int c = 0; c <= j; ++c) {
-        const double hc = hs[c];
-        const T *vc = V + (int64_t)c * ld + base;
+        const double hr = hs[2 * c], hi = hs[2 * c + 1];
+        const T2 *vc = reinterpret_cast<const T2 *>(V + (int64_t)c * ld + base);
 #pragma unroll
-        for (int t = 0; t < VCHUNK / 256; ++t) {
-            const int64_t i = i0 + t * 256 + threadIdx.x;
-            if (i < n) acc[t] -= hc * (double)vc[i];
+        for (int t = 0; t < PPT; ++t) {
+            const int64_t i = p0 + t * 256 + threadIdx.x;
+            if (i < np) {
+                const T2 v = vc[i];
+                xr[t] -= hr * (double)v.x - hi * (double)v.y;
+                xi[t] -= hr * (double)v.y + hi * (double)v.x;
+            }
         }
     }
     double nrm = 0.0;
 #pragma unroll
-    for (int t = 0; t < VCHUNK / 256; ++t) {
-        const int64_t i = i0 + t * 256 + threadIdx.x;
-        if (i < n) {
-            const T v = (T)acc[t];
-            w[base + i] = v;
-            nrm += (double)v * (double)v;
+    for (int t = 0; t < PPT; ++t) {
+        const int64_t i = p0 + t * 256 + threadIdx.x;
+        if (i < np) {
+            const T2 v{(T)xr[t], (T)xi[t]};
+            wp[i] = v;
+            nrm += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
         }
     }
-    nrm = block_sum256(nrm, lds);
-    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * maxcols] = nrm;
+    wave_store<T>(nrm, part + ((int64_t)blockIdx.x * NPW + (threadIdx.x >> 6)) * maxcols);
 }
 
-// Partial sums of ||x||^2 (and optionally of ||y||^2 into column 1).
+// Per-wave partials of ||x||^2.
 template <class T>
 __global__ void __launch_bounds__(256) k_norm2(const int64_t *__restrict__ off, const int64_t *__restrict__ len,
                                                const int32_t *__restrict__ blkoff, int ns,
                                                const int32_t *__restrict__ mask, const T *__restrict__ x,
                                                double *__restrict__ part, int maxcols) {
-    __shared__ double lds[4];
     const int s = find_sys(blkoff, ns, blockIdx.x);
     if (mask && !mask[s]) return;
     const int64_t base = off[s], n = len[s];
@@ -225,8 +258,7 @@ __global__ void __launch_bounds__(256) k_norm2(const int64_t *__restrict__ off, 
         const int64_t i = i0 + t * 256 + threadIdx.x;
         if (i < n) { const double v = (double)x[base + i]; a += v * v; }
     }
-    a = block_sum256(a, lds);
-    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * maxcols] = a;
+    wave_store<T>(a, part + ((int64_t)blockIdx.x * NPW + (threadIdx.x >> 6)) * maxcols);
 }
 
 // y = a_s * x (a_s = scal[s] or 1/scal[s]); optional second destination.
@@ -254,34 +286,40 @@ __global__ void __launch_bounds__(256) k_scale(const int64_t *__restrict__ off, 
     }
 }
 
-// y (+)= sum_{c<k} V_c coef[s][c]  (k = kcnt[s]); used for the GMRES solution update.
+// y = sum_{c<k} V_c coef[s][c] (complex coefficients), k = kcnt[s].
 template <class T>
 __global__ void __launch_bounds__(256) k_lincomb(const int64_t *__restrict__ off, const int64_t *__restrict__ len,
                                                  const int32_t *__restrict__ blkoff, int ns,
                                                  const int32_t *__restrict__ mask, const int32_t *__restrict__ kcnt,
                                                  const T *__restrict__ V, int64_t ld, const double *__restrict__ coef,
                                                  int ldc, T *__restrict__ y) {
+    using T2 = typename V2<T>::t;
     const int s = find_sys(blkoff, ns, blockIdx.x);
     if (mask && !mask[s]) return;
     const int k = kcnt[s];
-    const int64_t base = off[s], n = len[s];
-    const int64_t i0 = (int64_t)(blockIdx.x - blkoff[s]) * VCHUNK;
-    double acc[VCHUNK / 256];
+    const int64_t base = off[s], np = len[s] / 2;
+    const int64_t p0 = (int64_t)(blockIdx.x - blkoff[s]) * (VCHUNK / 2);
+    double xr[PPT], xi[PPT];
 #pragma unroll
-    for (int t = 0; t < VCHUNK / 256; ++t) acc[t] = 0.0;
+    for (int t = 0; t < PPT; ++t) xr[t] = xi[t] = 0.0;
     for (int c = 0; c < k; ++c) {
-        const double a = coef[(int64_t)s * ldc + c];
-        const T *vc = V + (int64_t)c * ld + base;
+        const double ar = coef[(int64_t)s * ldc + 2 * c], ai = coef[(int64_t)s * ldc + 2 * c + 1];
+        const T2 *vc = reinterpret_cast<const T2 *>(V + (int64_t)c * ld + base);
 #pragma unroll
-        for (int t = 0; t < VCHUNK / 256; ++t) {
-            const int64_t i = i0 + t * 256 + threadIdx.x;
-            if (i < n) acc[t] += a * (double)vc[i];
+        for (int t = 0; t < PPT; ++t) {
+            const int64_t i = p0 + t * 256 + threadIdx.x;
+            if (i < np) {
+                const T2 v = vc[i];
+                xr[t] += ar * (double)v.x - ai * (double)v.y;
+                xi[t] += ar * (double)v.y + ai * (double)v.x;
+            }
         }
     }
+    T2 *yp = reinterpret_cast<T2 *>(y + base);
 #pragma unroll
-    for (int t = 0; t < VCHUNK / 256; ++t) {
-        const int64_t i = i0 + t * 256 + threadIdx.x;
-        if (i < n) y[base + i] = (T)acc[t];
+    for (int t = 0; t < PPT; ++t) {
+        const int64_t i = p0 + t * 256 + threadIdx.x;
+        if (i < np) yp[i] = T2{(T)xr[t], (T)xi[t]};
     }
 }
 
@@ -303,19 +341,29 @@ __global__ void __launch_bounds__(256) k_axpy(const int64_t *__restrict__ off, c
     }
 }
 
-// Start of a GMRES cycle: beta = ||r||; running systems whose beta/bnorm <= rtol stop.
-// Initialises g = (beta, 0, ...), jcnt = 0, active flag, and 1/beta for v_0.
+__device__ __forceinline__ double slot_sum(const double *part, int maxcols, int b0, int b1, int col) {
+    double a = 0.0;
+    for (int b = b0 * NPW + (int)threadIdx.x; b < b1 * NPW; b += blockDim.x) a += part[(int64_t)b * maxcols + col];
+    return wave_sum(a);  // blockDim.x == 64
+}
+
+// Start of a GMRES cycle (one wave per system): beta = ||r||; systems with
+// beta/bnorm <= rtol stop; otherwise g = (beta, 0, ...), jcnt = 0, active = 1.
 __global__ void k_cycle_start(int ns, const int32_t *__restrict__ blkoff, const double *__restrict__ part,
                               int maxcols, int32_t *__restrict__ running, int32_t *__restrict__ active,
                               int32_t *__restrict__ jcnt, const double *__restrict__ bnorm, double rtol,
                               double *__restrict__ g, int m, double *__restrict__ beta_out,
                               double *__restrict__ resid_out, int32_t *__restrict__ iters, int max_iter) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = blockIdx.x;
     if (s >= ns) return;
-    if (!running[s]) { active[s] = 0; return; }
-    double b2 = 0.0;
-    for (int b = blkoff[s]; b < blkoff[s + 1]; ++b) b2 += part[(int64_t)b * maxcols];
-    const double beta = sqrt(b2);
+    if (!running[s]) {
+        if (threadIdx.x == 0) active[s] = 0;
+        return;
+    }
+    const double beta = sqrt(slot_sum(part, maxcols, blkoff[s], blkoff[s + 1], 0));
+    double *gs = g + (int64_t)s * 2 * (m + 1);
+    for (int i = threadIdx.x; i < 2 * (m + 1); i += blockDim.x) gs[i] = 0.0;
+    if (threadIdx.x != 0) return;
     const double rel = bnorm[s] > 0.0 ? beta / bnorm[s] : 0.0;
     resid_out[s] = rel;
     beta_out[s] = beta;
@@ -326,68 +374,130 @@ __global__ void k_cycle_start(int ns, const int32_t *__restrict__ blkoff, const 
         return;
     }
     active[s] = 1;
-    double *gs = g + (int64_t)s * (m + 1);
     gs[0] = beta;
-    for (int i = 1; i <= m; ++i) gs[i] = 0.0;
 }
 
-// After the dots/update of Arnoldi step j: finish column j of H (FP64), apply the
-// previous Givens rotations, build the new one, update g and the residual estimate.
+// After Arnoldi step j (one wave per system): h_{j+1,j} = ||w||, apply the previous
+// complex Givens rotations to column j of H, build the new one, update g.
+// Rotation G = [[c, s], [-conj(s), c]] with c real: G [a; b] = [r; 0].
 __global__ void k_arnoldi_finish(int ns, const int32_t *__restrict__ blkoff, const double *__restrict__ part,
                                  int maxcols, int32_t *__restrict__ active, int32_t *__restrict__ jcnt,
                                  const double *__restrict__ hcol, int ldh, double *__restrict__ H,
                                  double *__restrict__ cs, double *__restrict__ sn, double *__restrict__ g,
-                                 double *__restrict__ hnext, const double *__restrict__ bnorm, double rtol, int m,
-                                 int32_t *__restrict__ iters, int max_iter, double *__restrict__ resid_est) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+                                 double *__restrict__ hnext, const double *__restrict__ bnorm,
+                                 const double *__restrict__ rtol_d, int m, int32_t *__restrict__ iters, int max_iter,
+                                 double *__restrict__ resid_est) {
+    __shared__ double colr[1025], coli[1025], csl[1024], snr[1024], sni[1024];
+    const int s = blockIdx.x;
     if (s >= ns || !active[s]) return;
     const int j = jcnt[s];
-    double w2 = 0.0;
-    for (int b = blkoff[s]; b < blkoff[s + 1]; ++b) w2 += part[(int64_t)b * maxcols];
-    const double hn = sqrt(w2);
-    double *Hs = H + (int64_t)s * (m + 1) * m;  // column-major (m+1) x m
-    double *col = Hs + (int64_t)j * (m + 1);
+    const double hn = sqrt(slot_sum(part, maxcols, blkoff[s], blkoff[s + 1], 0));
     const double *hc = hcol + (int64_t)s * ldh;
-    for (int i = 0; i <= j; ++i) col[i] = hc[i];
-    double *css = cs + (int64_t)s * m, *sns = sn + (int64_t)s * m, *gs = g + (int64_t)s * (m + 1);
-    for (int i = 0; i < j; ++i) {
-        const double t = css[i] * col[i] + sns[i] * col[i + 1];
-        col[i + 1] = -sns[i] * col[i] + css[i] * col[i + 1];
-        col[i] = t;
+    double *css = cs + (int64_t)s * m, *sns = sn + (int64_t)s * 2 * m;
+    for (int i = threadIdx.x; i <= j; i += blockDim.x) {
+        colr[i] = hc[2 * i];
+        coli[i] = hc[2 * i + 1];
+        if (i < j) {
+            csl[i] = css[i];
+            snr[i] = sns[2 * i];
+            sni[i] = sns[2 * i + 1];
+        }
     }
-    const double a = col[j], b = hn;
-    const double den = hypot(a, b);
-    double c = 1.0, sv = 0.0, r = a;
-    if (den > 0.0) { c = a / den; sv = b / den; r = den; }
-    css[j] = c;
-    sns[j] = sv;
-    col[j] = r;
-    col[j + 1] = 0.0;
-    gs[j + 1] = -sv * gs[j];
-    gs[j] = c * gs[j];
-    hnext[s] = hn;
-    jcnt[s] = j + 1;
-    iters[s] += 1;
-    const double est = fabs(gs[j + 1]) / bnorm[s];
-    resid_est[s] = est;
-    const bool breakdown = !(hn > 1e-300) || !(den > 0.0);
-    if (est <= rtol || breakdown || j + 1 >= m || iters[s] >= max_iter || !isfinite(est)) active[s] = 0;
+    __syncthreads();
+    double *gs = g + (int64_t)s * 2 * (m + 1);
+    if (threadIdx.x == 0) {
+        double br = hn, bi = 0.0;  // entry j+1 of the column (real on input)
+        colr[j + 1] = br;
+        coli[j + 1] = bi;
+        for (int i = 0; i < j; ++i) {
+            const double c = csl[i], sr = snr[i], si = sni[i];
+            const double ar = colr[i], ai = coli[i], cr = colr[i + 1], ci = coli[i + 1];
+            // t = c a + s b ;  b' = -conj(s) a + c b
+            colr[i] = c * ar + (sr * cr - si * ci);
+            coli[i] = c * ai + (sr * ci + si * cr);
+            colr[i + 1] = -(sr * ar + si * ai) + c * cr;
+            coli[i + 1] = -(sr * ai - si * ar) + c * ci;
+        }
+        const double ar = colr[j], ai = coli[j], bnr = colr[j + 1], bni = coli[j + 1];
+        const double na = hypot(ar, ai), nb = hypot(bnr, bni);
+        const double den = hypot(na, nb);
+        double c = 1.0, sr = 0.0, si = 0.0, rr = ar, ri = ai;
+        if (den > 0.0) {
+            if (na == 0.0) {
+                c = 0.0; sr = 1.0; si = 0.0; rr = bnr; ri = bni;  // rotation maps b to the top
+                // with a = 0: [c a + s b] = b, and -conj(s) a + c b = 0
+            } else {
+                const double ur = ar / na, ui = ai / na;  // a/|a|
+                c = na / den;
+                // s = (a/|a|) conj(b) / den
+                sr = (ur * bnr + ui * bni) / den;
+                si = (ui * bnr - ur * bni) / den;
+                rr = ur * den;
+                ri = ui * den;
+            }
+        }
+        css[j] = c;
+        sns[2 * j] = sr;
+        sns[2 * j + 1] = si;
+        colr[j] = rr;
+        coli[j] = ri;
+        colr[j + 1] = 0.0;
+        coli[j + 1] = 0.0;
+        // g_{j+1} = -conj(s) g_j ; g_j = c g_j
+        const double gr = gs[2 * j], gi = gs[2 * j + 1];
+        gs[2 * (j + 1)] = -(sr * gr + si * gi);
+        gs[2 * (j + 1) + 1] = -(sr * gi - si * gr);
+        gs[2 * j] = c * gr;
+        gs[2 * j + 1] = c * gi;
+        hnext[s] = hn;
+        jcnt[s] = j + 1;
+        iters[s] += 1;
+        const double est = hypot(gs[2 * (j + 1)], gs[2 * (j + 1) + 1]) / bnorm[s];
+        resid_est[s] = est;
+        const bool breakdown = !(hn > 1e-300) || !(den > 0.0);
+        if (est <= *rtol_d || breakdown || j + 1 >= m || iters[s] >= max_iter || !isfinite(est)) active[s] = 0;
+    }
+    __syncthreads();
+    double *Hs = H + (int64_t)s * 2 * (m + 1) * m + (int64_t)j * 2 * (m + 1);  // column j, complex
+    for (int i = threadIdx.x; i <= j + 1; i += blockDim.x) {
+        Hs[2 * i] = colr[i];
+        Hs[2 * i + 1] = coli[i];
+    }
 }
 
-// y = H^{-1} g on the first k = jcnt[s] columns (upper triangular after Givens).
+// y = H^{-1} g on the first k = jcnt[s] columns (upper triangular, complex); one wave
+// per system, column-oriented back substitution.
 __global__ void k_hsolve(int ns, const int32_t *__restrict__ running, const int32_t *__restrict__ jcnt,
                          const double *__restrict__ H, const double *__restrict__ g, double *__restrict__ y, int m) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ double rr[1025], ri[1025];
+    const int s = blockIdx.x;
     if (s >= ns || !running[s]) return;
     const int k = jcnt[s];
-    const double *Hs = H + (int64_t)s * (m + 1) * m;
-    const double *gs = g + (int64_t)s * (m + 1);
-    double *ys = y + (int64_t)s * (m + 1);
+    const double *Hs = H + (int64_t)s * 2 * (m + 1) * m;
+    const double *gs = g + (int64_t)s * 2 * (m + 1);
+    double *ys = y + (int64_t)s * 2 * (m + 1);
+    for (int i = threadIdx.x; i < k; i += blockDim.x) {
+        rr[i] = gs[2 * i];
+        ri[i] = gs[2 * i + 1];
+    }
+    __syncthreads();
     for (int i = k - 1; i >= 0; --i) {
-        double acc = gs[i];
-        for (int c = i + 1; c < k; ++c) acc -= Hs[(int64_t)c * (m + 1) + i] * ys[c];
-        const double d = Hs[(int64_t)i * (m + 1) + i];
-        ys[i] = d != 0.0 ? acc / d : 0.0;
+        const double *col = Hs + (int64_t)i * 2 * (m + 1);
+        const double dr = col[2 * i], di = col[2 * i + 1];
+        const double den = dr * dr + di * di;
+        // y_i = r_i / d
+        const double yr = den > 0.0 ? (rr[i] * dr + ri[i] * di) / den : 0.0;
+        const double yi = den > 0.0 ? (ri[i] * dr - rr[i] * di) / den : 0.0;
+        for (int r = threadIdx.x; r < i; r += blockDim.x) {
+            const double hr = col[2 * r], hi = col[2 * r + 1];
+            rr[r] -= hr * yr - hi * yi;
+            ri[r] -= hr * yi + hi * yr;
+        }
+        if (threadIdx.x == 0) {
+            ys[2 * i] = yr;
+            ys[2 * i + 1] = yi;
+        }
+        __syncthreads();
     }
 }
 
@@ -402,16 +512,15 @@ __global__ void k_zero_flagged(const int64_t *__restrict__ off, const int64_t *_
     if (dirs[s][i]) { x[off[s] + 2 * i] = (T)0; x[off[s] + 2 * i + 1] = (T)0; }
 }
 
-// out[s] = sqrt(sum of partials); with check: resid[s] = out/bnorm, running[s] = 0 if <= rtol.
+// out[s] = sqrt(sum of partials); with bnorm: resid[s] = out/bnorm, running[s] = 0 if <= rtol.
 __global__ void k_norm_finish(int ns, const int32_t *__restrict__ blkoff, const double *__restrict__ part,
                               int maxcols, const int32_t *__restrict__ mask, double *__restrict__ out,
                               const double *__restrict__ bnorm, double rtol, double *__restrict__ resid,
                               int32_t *__restrict__ running) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = blockIdx.x;
     if (s >= ns || (mask && !mask[s])) return;
-    double a = 0.0;
-    for (int b = blkoff[s]; b < blkoff[s + 1]; ++b) a += part[(int64_t)b * maxcols];
-    const double nrm = sqrt(a);
+    const double nrm = sqrt(slot_sum(part, maxcols, blkoff[s], blkoff[s + 1], 0));
+    if (threadIdx.x != 0) return;
     out[s] = nrm;
     if (bnorm) {
         const double rel = bnorm[s] > 0.0 ? nrm / bnorm[s] : 0.0;
@@ -426,9 +535,9 @@ __global__ void k_norm_finish(int ns, const int32_t *__restrict__ blkoff, const 
 
 template <class T>
 void launch_dots(const Batch &B, const int32_t *mask, const int32_t *jcnt, const T *V, int64_t ld, const T *w,
-                 double *part, hipStream_t st) {
+                 double *part, int cplx, hipStream_t st) {
     VGUARD(B);
-    k_dots<T><<<VGRID(B.vs)>>>(B.off.p, B.len.p, B.vs.blkoff.p, B.ns, mask, jcnt, V, ld, w, part, B.maxcols);
+    k_dots<T><<<VGRID(B.vs)>>>(B.off.p, B.len.p, B.vs.blkoff.p, B.ns, mask, jcnt, V, ld, w, part, B.maxcols, cplx);
     THM_HIP(hipGetLastError());
 }
 template <class T>
@@ -467,35 +576,37 @@ void launch_axpy(const Batch &B, const int32_t *mask, const double *scal, const 
 }
 void launch_norm_finish(const Batch &B, const double *part, const int32_t *mask, double *out, const double *bnorm,
                         double rtol, double *resid, int32_t *running, hipStream_t st) {
-    k_norm_finish<<<(B.ns + 63) / 64, 64, 0, st>>>(B.ns, B.vs.blkoff.p, part, B.maxcols, mask, out, bnorm, rtol,
+    k_norm_finish<<<B.ns, 64, 0, st>>>(B.ns, B.vs.blkoff.p, part, B.maxcols, mask, out, bnorm, rtol,
                                                    resid, running);
     THM_HIP(hipGetLastError());
 }
 void launch_reduce_cols(const Batch &B, const int32_t *mask, const int32_t *jcnt, int ncols_fixed,
                         const double *part, double *out, int ldo, int accumulate, hipStream_t st) {
-    k_reduce_cols<<<B.ns, 64, 0, st>>>(B.vs.blkoff.p, B.ns, mask, jcnt, ncols_fixed, part, B.maxcols, out, ldo,
+    const int chunks = ncols_fixed > 0 ? (ncols_fixed + 15) / 16 : (B.maxcols + 15) / 16;
+    k_reduce_cols<<<dim3(B.ns, chunks), 256, 0, st>>>(B.vs.blkoff.p, B.ns, mask, jcnt, ncols_fixed, part, B.maxcols, out, ldo,
                                        accumulate);
     THM_HIP(hipGetLastError());
 }
 void launch_cycle_start(const Batch &B, const double *part, int32_t *running, int32_t *active, int32_t *jcnt,
                         const double *bnorm, double rtol, double *g, int m, double *beta, double *resid,
                         int32_t *iters, int max_iter, hipStream_t st) {
-    k_cycle_start<<<(B.ns + 63) / 64, 64, 0, st>>>(B.ns, B.vs.blkoff.p, part, B.maxcols, running, active, jcnt,
+    k_cycle_start<<<B.ns, 64, 0, st>>>(B.ns, B.vs.blkoff.p, part, B.maxcols, running, active, jcnt,
                                                    bnorm, rtol, g, m, beta, resid, iters, max_iter);
     THM_HIP(hipGetLastError());
 }
 void launch_arnoldi_finish(const Batch &B, const double *part, int32_t *active, int32_t *jcnt, const double *hcol,
                            int ldh, double *H, double *cs, double *sn, double *g, double *hnext,
-                           const double *bnorm, double rtol, int m, int32_t *iters, int max_iter, double *est,
-                           hipStream_t st) {
-    k_arnoldi_finish<<<(B.ns + 63) / 64, 64, 0, st>>>(B.ns, B.vs.blkoff.p, part, B.maxcols, active, jcnt, hcol,
-                                                      ldh, H, cs, sn, g, hnext, bnorm, rtol, m, iters, max_iter,
+                           const double *bnorm, const double *rtol_d, int m, int32_t *iters, int max_iter,
+                           double *est, hipStream_t st) {
+    if (m > 1024) fail(THM_EINVAL, "restart must be <= 1024");
+    k_arnoldi_finish<<<B.ns, 64, 0, st>>>(B.ns, B.vs.blkoff.p, part, B.maxcols, active, jcnt, hcol,
+                                                      ldh, H, cs, sn, g, hnext, bnorm, rtol_d, m, iters, max_iter,
                                                       est);
     THM_HIP(hipGetLastError());
 }
 void launch_hsolve(const Batch &B, const int32_t *running, const int32_t *jcnt, const double *H, const double *g,
                    double *y, int m, hipStream_t st) {
-    k_hsolve<<<(B.ns + 63) / 64, 64, 0, st>>>(B.ns, running, jcnt, H, g, y, m);
+    k_hsolve<<<B.ns, 64, 0, st>>>(B.ns, running, jcnt, H, g, y, m);
     THM_HIP(hipGetLastError());
 }
 template <class T>
@@ -507,7 +618,7 @@ void launch_zero_flagged(const Batch &B, const uint8_t *const *dirs, T *x, hipSt
 
 #define INST_T(T)                                                                                            \
     template void launch_dots<T>(const Batch &, const int32_t *, const int32_t *, const T *, int64_t,         \
-                                 const T *, double *, hipStream_t);                                          \
+                                 const T *, double *, int, hipStream_t);                                     \
     template void launch_cgs_update<T>(const Batch &, const int32_t *, const int32_t *, const T *, int64_t,   \
                                        T *, const double *, int, double *, hipStream_t);                     \
     template void launch_norm2<T>(const Batch &, const int32_t *, const T *, double *, hipStream_t);          \

@@ -1,10 +1,11 @@
 // Block preconditioner diag(K, K)^{-1} of eq. (11) with an exact factorised K^{-1}:
 //  1. static condensation of the cell-interior DoFs (per-cell dense inverse),
-//  2. block-tridiagonal LU over layers of skeleton (edge/face) DoFs stacked along
-//     the last axis, with explicitly inverted pivot blocks S_k^{-1} and the
-//     couplings Lf_k = B_k S_{k-1}^{-1} (and Lf_k^T) stored densely.
-// Application to the two right-hand sides (real and imaginary halves) is a chain
-// of dense GEMVs (one launch per layer step, batched over systems).
+//  2. block cyclic reduction of the block-tridiagonal system on the skeleton
+//     (edge/face) DoFs, layered along the last axis: every level eliminates the
+//     odd-positioned blocks (explicit dense inverses) and couples the even ones.
+// Application to the two right-hand sides (real and imaginary halves) is one
+// batched multi-GEMV launch per level and direction; systems whose matrices are
+// identical share one factor and are served by the same matrix rows.
 #include "kernels.h"
 
 namespace thm {
@@ -276,17 +277,20 @@ __global__ void k_gj_pivot(const InvDesc *ds, int nd, int col, int parity, int32
     }
 }
 
+// One block per (row i, 256-column chunk) of each matrix: no per-element division.
 __global__ void __launch_bounds__(256) k_gj_update(const InvDesc *__restrict__ ds, const int32_t *__restrict__ blkoff,
                                                    int nd, int col, int parity) {
     const int di = find_sys2(blkoff, nd, blockIdx.x);
     const InvDesc d = ds[di];
     const int n = d.n;
     if (col >= n) return;
-    const int64_t id = (int64_t)(blockIdx.x - blkoff[di]) * 256 + threadIdx.x;
-    if (id >= (int64_t)n * n) return;
+    const int nch = (n + 255) / 256;
+    const int local = blockIdx.x - blkoff[di];
+    const int i = local / nch;
+    const int j = (local - i * nch) * 256 + threadIdx.x;
+    if (i >= n || j >= n) return;
     const double *Ain = parity ? d.W : d.A;
     double *Aout = parity ? d.A : d.W;
-    const int i = (int)(id / n), j = (int)(id % n);
     const int p = d.piv[col];
     const double pv = Ain[(int64_t)p * n + col];
     const double ipv = pv != 0.0 ? 1.0 / pv : 0.0;
@@ -300,7 +304,7 @@ __global__ void __launch_bounds__(256) k_gj_update(const InvDesc *__restrict__ d
         const double e = (j == col) ? 0.0 : Ain[(int64_t)src * n + j];
         out = e - f * pr;
     }
-    Aout[id] = out;
+    Aout[(int64_t)i * n + j] = out;
 }
 
 __global__ void k_gj_perm_build(const InvDesc *ds, int nd) {
@@ -322,23 +326,25 @@ __global__ void __launch_bounds__(256) k_gj_perm_apply(const InvDesc *__restrict
     const int di = find_sys2(blkoff, nd, blockIdx.x);
     const InvDesc d = ds[di];
     const int n = d.n;
-    const int64_t id = (int64_t)(blockIdx.x - blkoff[di]) * 256 + threadIdx.x;
-    if (id >= (int64_t)n * n) return;
+    const int nch = (n + 255) / 256;
+    const int local = blockIdx.x - blkoff[di];
+    const int i = local / nch;
+    const int j = (local - i * nch) * 256 + threadIdx.x;
+    if (i >= n || j >= n) return;
     const double *res = (n % 2 == 0) ? d.A : d.W;
-    const int i = (int)(id / n), j = (int)(id % n);
-    d.out[id] = res[(int64_t)i * n + d.piv[n + j]];
+    d.out[(int64_t)i * d.ldo + j] = res[(int64_t)i * n + d.piv[n + j]];
 }
 
 void launch_invert_batched(const std::vector<InvDesc> &d, int32_t *status, hipStream_t st, DBuf<InvDesc> &scratch) {
     if (d.empty()) return;
     int nmax = 0;
-    std::vector<int64_t> elems(d.size());
+    std::vector<int64_t> blocks(d.size());
     for (size_t i = 0; i < d.size(); ++i) {
         nmax = std::max(nmax, d[i].n);
-        elems[i] = (int64_t)d[i].n * d[i].n;
+        blocks[i] = (int64_t)d[i].n * ((d[i].n + 255) / 256);
     }
     Sched sc;
-    sc.build(elems, 256, st);
+    sc.build(blocks, 1, st);
     scratch.upload(d, st);
     const int nd = (int)d.size();
     for (int col = 0; col < nmax; ++col) {
@@ -352,24 +358,36 @@ void launch_invert_batched(const std::vector<InvDesc> &d, int32_t *status, hipSt
     THM_HIP(hipStreamSynchronize(st));  // keeps the schedule alive until the kernels finished
 }
 
-__global__ void k_transpose(const double *A, int m, int n, double *At) {
+__global__ void k_transpose(const double *A, int m, int n, int lda, double *At, int ldt, double alpha) {
     __shared__ double t[32][33];
     const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
     const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;  // 32 x 8 threads
     for (int r = ty; r < 32; r += 8) {
         const int i = by + r, j = bx + tx;
-        if (i < m && j < n) t[r][tx] = A[(int64_t)i * n + j];
+        if (i < m && j < n) t[r][tx] = A[(int64_t)i * lda + j];
     }
     __syncthreads();
     for (int r = ty; r < 32; r += 8) {
         const int j = bx + r, i = by + tx;
-        if (i < m && j < n) At[(int64_t)j * m + i] = t[tx][r];
+        if (i < m && j < n) At[(int64_t)j * ldt + i] = alpha * t[tx][r];
     }
 }
-void launch_transpose(const double *A, int m, int n, double *At, hipStream_t st) {
+void launch_transpose(const double *A, int m, int n, int lda, double *At, int ldt, double alpha, hipStream_t st) {
     if (!m || !n) return;
     dim3 g((n + 31) / 32, (m + 31) / 32);
-    k_transpose<<<g, 256, 0, st>>>(A, m, n, At);
+    k_transpose<<<g, 256, 0, st>>>(A, m, n, lda, At, ldt, alpha);
+    THM_HIP(hipGetLastError());
+}
+
+// mismatch[0] |= (a != b) over n entries (bitwise comparison of double arrays)
+__global__ void k_compare(const uint64_t *a, const uint64_t *b, int64_t n, int32_t *mismatch) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && a[i] != b[i]) *mismatch = 1;
+}
+void launch_compare(const void *a, const void *b, int64_t nbytes8, int32_t *mismatch, hipStream_t st) {
+    if (!nbytes8) return;
+    k_compare<<<(unsigned)((nbytes8 + 255) / 256), 256, 0, st>>>((const uint64_t *)a, (const uint64_t *)b, nbytes8,
+                                                                 mismatch);
     THM_HIP(hipGetLastError());
 }
 
@@ -415,74 +433,115 @@ __global__ void __launch_bounds__(256) k_cond_fwd(const PrecDesc *__restrict__ p
     ws[t] = acc;
 }
 
-// Wave-per-row GEMV on layer blocks.  MODE 0: forward step k (ws_k -= Lf_k ws_{k-1});
-// MODE 1: ys = blockdiag(S^{-1}) ws over all layers; MODE 2: backward step k
-// (ys_k -= Lf_{k+1}^T ys_{k+1}).
-template <class T, int MODE>
-__global__ void __launch_bounds__(256) k_layer_gemv(const PrecDesc *__restrict__ pd, const int64_t *__restrict__ soff,
-                                                    const int32_t *__restrict__ blkoff, int ns,
-                                                    const int32_t *__restrict__ mask, int k, T *__restrict__ wsb,
-                                                    T *__restrict__ ysb) {
+// Cyclic-reduction multi-GEMV.  A block owns RB consecutive rows of one task; its
+// four waves split the columns (each wave a contiguous quarter, lanes strided by
+// 64) and the partial sums are combined through LDS.  Members of the task's factor
+// group are processed MC at a time, so every loaded input element serves RB rows
+// and every matrix element MC members.
+//   subtract = 1:  y[row] = y[row] - sum_seg M[row, seg] x_seg   (reduction of RHS)
+//   subtract = 0:  y[row] =          sum_seg M[row, seg] x_seg   (back substitution)
+constexpr int RB = 8;  // rows per block
+template <class T> struct McOf { static constexpr int v = 4; };
+template <> struct McOf<double> { static constexpr int v = 2; };
+template <class T>
+__global__ void __launch_bounds__(256) k_bcr_gemv(const BcrTask *__restrict__ tasks, const int32_t *__restrict__ blkoff,
+                                                  int ntasks, const int32_t *__restrict__ memb_ptr,
+                                                  const int32_t *__restrict__ memb, const int64_t *__restrict__ soff,
+                                                  const int32_t *__restrict__ mask, T *__restrict__ wsb,
+                                                  T *__restrict__ ysb) {
     using T2 = typename P2<T>::t;
-    const int s = find_sys2(blkoff, ns, blockIdx.x);
-    if (mask && !mask[s]) return;
-    const PrecDesc d = pd[s];
+    constexpr int MC = McOf<T>::v;  // members per block
+    __shared__ T red[4][RB][MC][2];
+    const int t = find_sys2(blkoff, ntasks, blockIdx.x);
+    const BcrTask &tk = tasks[t];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t row = (int64_t)(blockIdx.x - blkoff[s]) * 4 + wave;
-    T2 *ws = reinterpret_cast<T2 *>(wsb + soff[s]);
-    T2 *ys = reinterpret_cast<T2 *>(ysb + soff[s]);
-    const T *M;
-    const T2 *x;
-    T2 *y;
-    int64_t ncols, rows;
-    if (MODE == 0) {
-        rows = d.bsize[k];
-        if (row >= rows) return;
-        ncols = d.bsize[k - 1];
-        M = reinterpret_cast<const T *>(d.lf) + d.lf_off[k] + row * ncols;
-        x = ws + d.boff[k - 1];
-        y = ws + d.boff[k] + row;
-    } else if (MODE == 1) {
-        if (row >= d.n_skel) return;
-        int lo = 0, hi = d.nlayers;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (d.boff[mid] <= row) lo = mid; else hi = mid;
-        }
-        const int64_t i = row - d.boff[lo];
-        ncols = d.bsize[lo];
-        M = reinterpret_cast<const T *>(d.sinv) + d.sinv_off[lo] + i * ncols;
-        x = ws + d.boff[lo];
-        y = ys + row;
-    } else {
-        rows = d.bsize[k];
-        if (row >= rows) return;
-        ncols = d.bsize[k + 1];
-        // Lf_{k+1}^T is b_k x b_{k+1}, stored at the same offset as Lf_{k+1}
-        M = reinterpret_cast<const T *>(d.lft) + d.lf_off[k + 1] + row * ncols;
-        x = ys + d.boff[k + 1];
-        y = ys + d.boff[k] + row;
-    }
-    T ar = 0, ai = 0;
-    for (int64_t j = lane; j < ncols; j += 64) {
-        const T a = M[j];
-        const T2 xv = x[j];
-        ar += a * xv.x;
-        ai += a * xv.y;
-    }
+    const int local = blockIdx.x - blkoff[t];
+    const int row0 = (local / tk.nmc) * RB;
+    const int mchunk = local % tk.nmc;
+    const int nr = min(RB, tk.rows - row0);
+    const T *M0 = reinterpret_cast<const T *>(tk.M) + (int64_t)row0 * tk.cols;
+    const int m0 = memb_ptr[tk.group], m1 = memb_ptr[tk.group + 1];
+    // this wave's column quarter [c0, c1) of the concatenated segments
+    const int q4 = (tk.cols + 3) / 4;
+    const int c0 = wave * q4, c1 = min(tk.cols, c0 + q4);
+    {
+        const int mb = m0 + mchunk * MC;
+        int sys[MC];
+        bool on[MC];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        ar += __shfl_xor(ar, o, 64);
-        ai += __shfl_xor(ai, o, 64);
-    }
-    if (lane == 0) {
-        if (MODE == 1) {
-            *y = T2{ar, ai};
-        } else {
-            T2 v = *y;
-            v.x -= ar;
-            v.y -= ai;
-            *y = v;
+        for (int q = 0; q < MC; ++q) {
+            sys[q] = mb + q < m1 ? memb[mb + q] : memb[m0];
+            on[q] = mb + q < m1 && (!mask || mask[sys[q]]);
+        }
+        bool any = false;
+#pragma unroll
+        for (int q = 0; q < MC; ++q) any = any || on[q];
+        if (!any) return;  // uniform across the block
+        T ar[RB][MC], ai[RB][MC];
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int q = 0; q < MC; ++q) ar[r][q] = ai[r][q] = 0;
+        int sbeg = 0;
+        for (int sg = 0; sg < tk.nseg; ++sg) {
+            const int len = tk.seg_len[sg];
+            const int lo = max(c0, sbeg), hi = min(c1, sbeg + len);
+            if (lo < hi) {
+                const T *src = tk.seg_src[sg] ? ysb : wsb;
+                const T2 *xq[MC];
+#pragma unroll
+                for (int q = 0; q < MC; ++q)
+                    xq[q] = reinterpret_cast<const T2 *>(src + soff[sys[q]]) + tk.seg_off[sg] - sbeg;
+#pragma unroll 2
+                for (int c = lo + lane; c < hi; c += 64) {
+                    T2 xv[MC];
+#pragma unroll
+                    for (int q = 0; q < MC; ++q) xv[q] = on[q] ? xq[q][c] : T2{0, 0};
+                    T a[RB];
+#pragma unroll
+                    for (int r = 0; r < RB; ++r) a[r] = r < nr ? M0[(int64_t)r * tk.cols + c] : (T)0;
+#pragma unroll
+                    for (int r = 0; r < RB; ++r)
+#pragma unroll
+                        for (int q = 0; q < MC; ++q) {
+                            ar[r][q] += a[r] * xv[q].x;
+                            ai[r][q] += a[r] * xv[q].y;
+                        }
+                }
+            }
+            sbeg += len;
+        }
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int q = 0; q < MC; ++q) {
+                T re = ar[r][q], im = ai[r][q];
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) {
+                    re += __shfl_xor(re, o, 64);
+                    im += __shfl_xor(im, o, 64);
+                }
+                if (lane == 0) {
+                    red[wave][r][q][0] = re;
+                    red[wave][r][q][1] = im;
+                }
+            }
+        __syncthreads();
+        if (threadIdx.x < RB * MC) {
+            const int r = threadIdx.x / MC, q = threadIdx.x % MC;
+            if (r < nr && on[q]) {
+                const T re = red[0][r][q][0] + red[1][r][q][0] + red[2][r][q][0] + red[3][r][q][0];
+                const T im = red[0][r][q][1] + red[1][r][q][1] + red[2][r][q][1] + red[3][r][q][1];
+                T2 *y = reinterpret_cast<T2 *>((tk.out_dst ? ysb : wsb) + soff[sys[q]]) + tk.out_off + row0 + r;
+                if (tk.subtract) {
+                    T2 v = *y;
+                    v.x -= re;
+                    v.y -= im;
+                    *y = v;
+                } else {
+                    *y = T2{re, im};
+                }
+            }
         }
     }
 }
@@ -506,8 +565,9 @@ __global__ void __launch_bounds__(256) k_cond_bwd(const PrecDesc *__restrict__ p
         return;
     }
     const T2 *r = reinterpret_cast<const T2 *>(rb + off[s]);
-    const int64_t c = (g - d.cell_off) / d.n_int;
-    const int m = (int)((g - d.cell_off) % d.n_int);
+    const int gi = (int)(g - d.cell_off);
+    const int64_t c = gi / d.n_int;
+    const int m = gi - (int)c * d.n_int;
     const T *Ki = reinterpret_cast<const T *>(d.kiinv) + (c * d.n_int + m) * d.n_int;
     const T2 *ri = r + d.cell_off + c * d.n_int;
     T2 acc{0, 0};
@@ -531,15 +591,12 @@ void launch_prec_apply(const PrecBatch &P, const PrecDesc *d, const int64_t *off
                        const T *r, T *x, T *ws, T *ys, hipStream_t st) {
     if (P.skel.nblocks)
         k_cond_fwd<T><<<P.skel.nblocks, 256, 0, st>>>(d, off, P.soff.p, P.skel.blkoff.p, ns, mask, r, ws);
-    for (int k = 1; k < P.maxlayers; ++k)
-        if (P.fwd[k].nblocks)
-            k_layer_gemv<T, 0><<<P.fwd[k].nblocks, 256, 0, st>>>(d, P.soff.p, P.fwd[k].blkoff.p, ns, mask, k, ws, ys);
-    if (P.skel_rows.nblocks)
-        k_layer_gemv<T, 1><<<P.skel_rows.nblocks, 256, 0, st>>>(d, P.soff.p, P.skel_rows.blkoff.p, ns, mask, 0, ws,
-                                                               ys);
-    for (int k = P.maxlayers - 2; k >= 0; --k)
-        if (P.bwd[k].nblocks)
-            k_layer_gemv<T, 2><<<P.bwd[k].nblocks, 256, 0, st>>>(d, P.soff.p, P.bwd[k].blkoff.p, ns, mask, k, ws, ys);
+    const int prec = sizeof(T) == 8 ? 0 : 1;
+    for (const PrecPhase &ph : P.phases)
+        if (ph.sched[prec].nblocks)
+            k_bcr_gemv<T><<<ph.sched[prec].nblocks, 256, 0, st>>>(ph.tasks[prec].p, ph.sched[prec].blkoff.p,
+                                                                   ph.ntasks, P.memb_ptr.p, P.memb.p, P.soff.p, mask,
+                                                                   ws, ys);
     if (P.dofs.nblocks)
         k_cond_bwd<T><<<P.dofs.nblocks, 256, 0, st>>>(d, off, P.soff.p, P.dofs.blkoff.p, ns, mask, r, ys, x);
     THM_HIP(hipGetLastError());

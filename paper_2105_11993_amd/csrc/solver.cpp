@@ -32,23 +32,21 @@ double now_ms() {
 void Krylov::init(const std::vector<int64_t> &n, int m_, hipStream_t st) {
     drop_graphs();
     m = m_;
-    B.init(n, m + 2, st);
+    B.init(n, 2 * (m + 1) + 2, st);
     const int ns = B.ns;
-    H.alloc((size_t)ns * (m + 1) * m);
+    H.alloc((size_t)ns * 2 * (m + 1) * m);  // complex, column-major (m+1) x m
     cs.alloc((size_t)ns * m);
-    sn.alloc((size_t)ns * m);
-    g.alloc((size_t)ns * (m + 1));
-    y.alloc((size_t)ns * (m + 1));
-    hcol.alloc((size_t)ns * (m + 1));
-    hcol2.alloc((size_t)ns * (m + 1));
+    sn.alloc((size_t)ns * 2 * m);
+    g.alloc((size_t)ns * 2 * (m + 1));
+    y.alloc((size_t)ns * 2 * (m + 1));
+    hcol.alloc((size_t)ns * 2 * (m + 1));
+    hcol2.alloc((size_t)ns * 2 * (m + 1));
     for (DBuf<double> *b : {&hnext, &bnorm, &beta, &resid, &est}) b->alloc(ns);
-    part.alloc((size_t)std::max(1, B.vs.nblocks) * B.maxcols);
+    rtol_d.alloc(1);
+    part.alloc((size_t)std::max(1, B.vs.nblocks) * NPW * B.maxcols);
     for (DBuf<int32_t> *b : {&running, &active, &jcnt, &iters}) b->alloc(ns);
-    if (!pinned) THM_HIP(hipHostMalloc((void **)&pinned, sizeof(int32_t) * 2 * std::max(ns, 1)));
-    else {
-        (void)hipHostFree(pinned);
-        THM_HIP(hipHostMalloc((void **)&pinned, sizeof(int32_t) * 2 * std::max(ns, 1)));
-    }
+    if (pinned) (void)hipHostFree(pinned);
+    THM_HIP(hipHostMalloc((void **)&pinned, sizeof(int32_t) * NEV * std::max(ns, 1)));
     for (auto &e : ev)
         if (!e) THM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
 }
@@ -107,17 +105,18 @@ static void arnoldi_step(Krylov &K, const KOps<T> &ops, const GmresParams &p, hi
     int32_t *act = K.active.p;
     ops.prec(cur, z, act);
     ops.apply(z, w, nullptr, act);
-    launch_dots<T>(B, act, K.jcnt.p, V, B.Ltot, w, K.part.p, st);
-    launch_reduce_cols(B, act, K.jcnt.p, 0, K.part.p, K.hcol.p, m + 1, 0, st);
-    launch_cgs_update<T>(B, act, K.jcnt.p, V, B.Ltot, w, K.hcol.p, m + 1, K.part.p, st);
+    const int ldh = 2 * (m + 1);
+    launch_dots<T>(B, act, K.jcnt.p, V, B.Ltot, w, K.part.p, p.cplx, st);
+    launch_reduce_cols(B, act, K.jcnt.p, 0, K.part.p, K.hcol.p, ldh, 0, st);
+    launch_cgs_update<T>(B, act, K.jcnt.p, V, B.Ltot, w, K.hcol.p, ldh, K.part.p, st);
     if (p.orth == THM_ORTH_CGS2) {
-        launch_dots<T>(B, act, K.jcnt.p, V, B.Ltot, w, K.part.p, st);
-        launch_reduce_cols(B, act, K.jcnt.p, 0, K.part.p, K.hcol2.p, m + 1, 0, st);
-        launch_reduce_cols(B, act, K.jcnt.p, 0, K.part.p, K.hcol.p, m + 1, 1, st);
-        launch_cgs_update<T>(B, act, K.jcnt.p, V, B.Ltot, w, K.hcol2.p, m + 1, K.part.p, st);
+        launch_dots<T>(B, act, K.jcnt.p, V, B.Ltot, w, K.part.p, p.cplx, st);
+        launch_reduce_cols(B, act, K.jcnt.p, 0, K.part.p, K.hcol2.p, ldh, 0, st);
+        launch_reduce_cols(B, act, K.jcnt.p, 0, K.part.p, K.hcol.p, ldh, 1, st);
+        launch_cgs_update<T>(B, act, K.jcnt.p, V, B.Ltot, w, K.hcol2.p, ldh, K.part.p, st);
     }
-    launch_arnoldi_finish(B, K.part.p, act, K.jcnt.p, K.hcol.p, m + 1, K.H.p, K.cs.p, K.sn.p, K.g.p, K.hnext.p,
-                          K.bnorm.p, p.rtol, m, K.iters.p, p.max_iter, K.est.p, st);
+    launch_arnoldi_finish(B, K.part.p, act, K.jcnt.p, K.hcol.p, ldh, K.H.p, K.cs.p, K.sn.p, K.g.p, K.hnext.p,
+                          K.bnorm.p, K.rtol_d.p, m, K.iters.p, p.max_iter, K.est.p, st);
     launch_scale<T, T>(B, act, K.hnext.p, 1, w, V, K.jcnt.p, B.Ltot, cur, st);
 }
 
@@ -125,7 +124,7 @@ template <class T>
 static hipGraphExec_t step_graph(Krylov &K, const KOps<T> &ops, const GmresParams &p, hipStream_t st) {
     const int key = TypeKey<T>::v * 2 + (ops.csign < 0 ? 1 : 0);
     Krylov::GraphSlot &s = K.slots[key];
-    if (s.exec && s.owner == ops.owner && s.orth == p.orth && s.rtol == p.rtol && s.max_iter == p.max_iter)
+    if (s.exec && s.owner == ops.owner && s.orth == p.orth && s.max_iter == p.max_iter && s.cplx == p.cplx)
         return s.exec;
     if (s.exec) (void)hipGraphExecDestroy(s.exec);
     if (s.graph) (void)hipGraphDestroy(s.graph);
@@ -145,6 +144,7 @@ static hipGraphExec_t step_graph(Krylov &K, const KOps<T> &ops, const GmresParam
     s.orth = p.orth;
     s.rtol = p.rtol;
     s.max_iter = p.max_iter;
+    s.cplx = p.cplx;
     s.csign = ops.csign;
     s.key_T = TypeKey<T>::v;
     return s.exec;
@@ -167,9 +167,11 @@ void gmres_run(Krylov &K, const KOps<T> &ops, const T *b, T *x, const int32_t *m
     launch_norm_finish(B, K.part.p, mask_in, K.bnorm.p, nullptr, 0.0, nullptr, nullptr, st);
     THM_HIP(hipMemcpyAsync(K.running.p, mask_in, sizeof(int32_t) * ns, hipMemcpyDeviceToDevice, st));
     THM_HIP(hipMemsetAsync(K.iters.p, 0, sizeof(int32_t) * ns, st));
+    K.rtol_h = p.rtol;
+    THM_HIP(hipMemcpyAsync(K.rtol_d.p, &K.rtol_h, sizeof(double), hipMemcpyHostToDevice, st));
     const bool graph = p.use_graph && ops.graphable;
     hipGraphExec_t exec = graph ? step_graph<T>(K, ops, p, st) : nullptr;
-    int32_t *hflag[2] = {K.pinned, K.pinned + ns};
+    int32_t *hflag[1] = {K.pinned};
     for (;;) {
         ops.apply(x, w, b, K.running.p);
         launch_norm2<T>(B, K.running.p, w, K.part.p, st);
@@ -179,20 +181,23 @@ void gmres_run(Krylov &K, const KOps<T> &ops, const T *b, T *x, const int32_t *m
         THM_HIP(hipStreamSynchronize(st));
         if (!any_set(hflag[0], ns)) break;
         launch_scale<T, T>(B, K.active.p, K.beta.p, 1, w, V, K.jcnt.p, B.Ltot, cur, st);
-        // Arnoldi steps; the host checks step j-1's flags while step j runs.
+        // Arnoldi steps; the host checks the flags of step j - LAG while later steps run.
+        constexpr int LAG = 3;
         for (int step = 0; step < m; ++step) {
             if (exec) THM_HIP(hipGraphLaunch(exec, st));
             else arnoldi_step<T>(K, ops, p, st);
-            const int sl = step & 1;
-            THM_HIP(hipMemcpyAsync(hflag[sl], K.active.p, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, st));
+            const int sl = step % Krylov::NEV;
+            THM_HIP(hipMemcpyAsync(K.pinned + (size_t)sl * ns, K.active.p, sizeof(int32_t) * ns,
+                                   hipMemcpyDeviceToHost, st));
             THM_HIP(hipEventRecord(K.ev[sl], st));
-            if (step > 0) {
-                THM_HIP(hipEventSynchronize(K.ev[sl ^ 1]));
-                if (!any_set(hflag[sl ^ 1], ns)) break;
+            if (step >= LAG) {
+                const int ol = (step - LAG) % Krylov::NEV;
+                THM_HIP(hipEventSynchronize(K.ev[ol]));
+                if (!any_set(K.pinned + (size_t)ol * ns, ns)) break;
             }
         }
         launch_hsolve(B, K.running.p, K.jcnt.p, K.H.p, K.g.p, K.y.p, m, st);
-        launch_lincomb<T>(B, K.running.p, K.jcnt.p, V, B.Ltot, K.y.p, m + 1, cur, st);
+        launch_lincomb<T>(B, K.running.p, K.jcnt.p, V, B.Ltot, K.y.p, 2 * (m + 1), cur, st);
         ops.prec(cur, z, K.running.p);
         launch_axpy<T, T>(B, K.running.p, nullptr, z, x, st);
     }
@@ -202,120 +207,6 @@ template void gmres_run<double>(Krylov &, const KOps<double> &, const double *, 
                                 const GmresParams &, hipStream_t);
 template void gmres_run<float>(Krylov &, const KOps<float> &, const float *, float *, const int32_t *,
                                const GmresParams &, hipStream_t);
-
-// ------------------------------------------------------------------ preconditioner setup
-void setup_precond(const std::vector<thm_system *> &all, hipStream_t st) {
-    std::vector<thm_system *> sys;
-    for (thm_system *s : all)
-        if (!s->prec_ready) sys.push_back(s);
-    if (sys.empty()) return;
-    const double t0 = now_ms();
-    DBuf<int32_t> status(1);
-    THM_HIP(hipMemsetAsync(status.p, 0, sizeof(int32_t), st));
-    std::vector<DBuf<double>> work0(sys.size()), work1(sys.size()), btmp(sys.size());
-    std::vector<DBuf<int32_t>> piv(sys.size());
-    int maxL = 0;
-    for (size_t i = 0; i < sys.size(); ++i) {
-        thm_system &S = *sys[i];
-        const Layering &L = S.L;
-        const Topo &t = S.topo;
-        S.Lskel_dof.upload(L.skel_dof, st);
-        S.Ldof_pos.upload(L.dof_pos, st);
-        S.Lcond_ptr.upload(L.cond_ptr, st);
-        S.Lcond_cell.upload(L.cond_cell, st);
-        S.Lcond_loc.upload(L.cond_loc, st);
-        S.Lbsize.upload(L.bsize, st);
-        S.Lboff.upload(L.boff, st);
-        S.Lsinv_off.upload(L.sinv_off, st);
-        S.Llf_off.upload(L.lf_off, st);
-        const int ne = t.n_loc - t.n_int;
-        S.kiinv.alloc((size_t)t.n_cells * t.n_int * t.n_int);
-        S.F.alloc((size_t)t.n_cells * ne * t.n_int);
-        DBuf<double> kcond((size_t)t.n_cells * ne * ne);
-        launch_condense((int)t.n_cells, t.n_loc, t.n_int, S.kel.p, S.cell_dofs.p, S.dir_d.p, S.kiinv.p, S.F.p, kcond.p,
-                        status.p, st);
-        S.sinv.alloc(L.sinv_total);
-        S.lf.alloc(std::max<int64_t>(L.lf_total, 1));
-        S.lft.alloc(std::max<int64_t>(L.lf_total, 1));
-        launch_fill(S.sinv.p, L.sinv_total, 0.0, st);
-        launch_fill(S.lf.p, L.lf_total, 0.0, st);
-        {
-            DBuf<int64_t> ti;
-            DBuf<int32_t> tk, tp, ts;
-            ti.upload(L.tgt_index, st);
-            tk.upload(L.tgt_kind, st);
-            tp.upload(L.tgt_ptr, st);
-            ts.upload(L.tgt_src, st);
-            launch_tgt_gather((int64_t)L.tgt_index.size(), ti.p, tk.p, tp.p, ts.p, kcond.p, S.sinv.p, S.lf.p, st);
-            THM_HIP(hipStreamSynchronize(st));
-        }
-        launch_dir_identity(L.n_skel, S.Lskel_dof.p, S.dir_d.p, S.Lboff.p, S.Lsinv_off.p, S.Lbsize.p, L.nlayers,
-                            S.sinv.p, st);
-        int bmax = 0;
-        for (int b : L.bsize) bmax = std::max(bmax, b);
-        work0[i].alloc((size_t)bmax * bmax);
-        work1[i].alloc((size_t)bmax * bmax);
-        btmp[i].alloc((size_t)bmax * bmax);
-        piv[i].alloc((size_t)2 * bmax);
-        maxL = std::max(maxL, L.nlayers);
-        THM_HIP(hipStreamSynchronize(st));
-    }
-    DBuf<GemmDesc> gscr;
-    DBuf<InvDesc> iscr;
-    Sched gsched;
-    for (int k = 0; k < maxL; ++k) {
-        std::vector<GemmDesc> g1, g2;
-        std::vector<InvDesc> inv;
-        for (size_t i = 0; i < sys.size(); ++i) {
-            thm_system &S = *sys[i];
-            const Layering &L = S.L;
-            if (k >= L.nlayers) continue;
-            const int bk = L.bsize[k];
-            double *sk = S.sinv.p + L.sinv_off[k];
-            THM_HIP(hipMemcpyAsync(work0[i].p, sk, sizeof(double) * bk * bk, hipMemcpyDeviceToDevice, st));
-            if (k > 0) {
-                const int bp = L.bsize[k - 1];
-                double *lfk = S.lf.p + L.lf_off[k];
-                THM_HIP(hipMemcpyAsync(btmp[i].p, lfk, sizeof(double) * bk * bp, hipMemcpyDeviceToDevice, st));
-                // Lf_k = B_k S_{k-1}^{-1}
-                g1.push_back({bk, bp, bp, 0, 0, btmp[i].p, S.sinv.p + L.sinv_off[k - 1], lfk, bp, bp, bp, 1.0, 0.0});
-                // S_k = A_k - Lf_k B_k^T
-                g2.push_back({bk, bk, bp, 0, 1, lfk, btmp[i].p, work0[i].p, bp, bp, bk, -1.0, 1.0});
-            }
-            inv.push_back({bk, work0[i].p, work1[i].p, sk, piv[i].p});
-        }
-        launch_gemm_batched(g1, st, gscr, gsched);
-        THM_HIP(hipStreamSynchronize(st));
-        launch_gemm_batched(g2, st, gscr, gsched);
-        THM_HIP(hipStreamSynchronize(st));
-        launch_invert_batched(inv, status.p, st, iscr);
-    }
-    for (thm_system *sp : sys) {
-        thm_system &S = *sp;
-        const Layering &L = S.L;
-        for (int k = 1; k < L.nlayers; ++k)
-            launch_transpose(S.lf.p + L.lf_off[k], L.bsize[k], L.bsize[k - 1], S.lft.p + L.lf_off[k], st);
-        S.sinv32.alloc(S.sinv.n);
-        S.lf32.alloc(S.lf.n);
-        S.lft32.alloc(S.lft.n);
-        S.kiinv32.alloc(std::max<size_t>(S.kiinv.n, 1));
-        S.F32.alloc(std::max<size_t>(S.F.n, 1));
-        launch_convert(S.sinv.p, S.sinv32.p, S.sinv.n, st);
-        launch_convert(S.lf.p, S.lf32.p, S.lf.n, st);
-        launch_convert(S.lft.p, S.lft32.p, S.lft.n, st);
-        launch_convert(S.kiinv.p, S.kiinv32.p, S.kiinv.n, st);
-        launch_convert(S.F.p, S.F32.p, S.F.n, st);
-    }
-    int32_t hs = 0;
-    THM_HIP(hipMemcpyAsync(&hs, status.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    THM_HIP(hipStreamSynchronize(st));
-    if (hs) fail(THM_ESINGULAR, "zero or non-finite pivot while factorising the block preconditioner");
-    const double dt = now_ms() - t0;
-    for (thm_system *s : sys) {
-        s->prec_ready = true;
-        s->prec_setup_ms = dt;
-    }
-}
 
 // ------------------------------------------------------------------ batched context
 void Ctx::build(const std::vector<thm_system *> &s, int m, hipStream_t stream) {
@@ -333,10 +224,20 @@ void Ctx::build(const std::vector<thm_system *> &s, int m, hipStream_t stream) {
     std::vector<const uint8_t *> hd(ns);
     std::vector<PrecDesc> p64(ns), p32(ns);
     std::vector<int64_t> soff(ns);
+    // factor groups in order of first appearance
+    std::vector<Factor *> groups;
+    std::vector<std::vector<int32_t>> members;
     int64_t so = 0;
-    int maxL = 0;
     for (int i = 0; i < ns; ++i) {
         thm_system &S = *sys[i];
+        Factor &f = *S.fac;
+        auto it = std::find(groups.begin(), groups.end(), &f);
+        if (it == groups.end()) {
+            groups.push_back(&f);
+            members.push_back({i});
+        } else {
+            members[it - groups.begin()].push_back(i);
+        }
         h64[i] = {S.n, S.k_rowptr.p, S.k_col.p, S.kval.p, S.c_rowptr.p, S.c_col.p, S.cval.p};
         h32[i] = {S.n, S.k_rowptr.p, S.k_col.p, S.kval32.p, S.c_rowptr.p, S.c_col.p, S.cval32.p};
         hd[i] = S.dir_d.p;
@@ -356,53 +257,98 @@ void Ctx::build(const std::vector<thm_system *> &s, int m, hipStream_t stream) {
         d.cond_ptr = S.Lcond_ptr.p;
         d.cond_cell = S.Lcond_cell.p;
         d.cond_loc = S.Lcond_loc.p;
-        d.boff = S.Lboff.p;
-        d.sinv_off = S.Lsinv_off.p;
-        d.lf_off = S.Llf_off.p;
-        d.bsize = S.Lbsize.p;
         p32[i] = d;
-        d.sinv = S.sinv.p;
-        d.lf = S.lf.p;
-        d.lft = S.lft.p;
-        d.kiinv = S.kiinv.p;
-        d.F = S.F.p;
+        d.kiinv = f.kiinv.p;
+        d.F = f.F.p;
         p64[i] = d;
-        p32[i].sinv = S.sinv32.p;
-        p32[i].lf = S.lf32.p;
-        p32[i].lft = S.lft32.p;
-        p32[i].kiinv = S.kiinv32.p;
-        p32[i].F = S.F32.p;
+        p32[i].kiinv = f.kiinv32.p;
+        p32[i].F = f.F32.p;
         soff[i] = so;
         so += 2 * nsk[i];
         so = (so + 63) & ~int64_t(63);
-        maxL = std::max(maxL, S.L.nlayers);
     }
     mat64.upload(h64, st);
     mat32.upload(h32, st);
     dirs.upload(hd, st);
     P.ns = ns;
-    P.maxlayers = maxL;
     P.d64.upload(p64, st);
     P.d32.upload(p32, st);
     P.soff.upload(soff, st);
     P.Stot = std::max<int64_t>(so, 64);
     P.skel.build(nsk, 256, st);
-    P.skel_rows.build(nsk, 4, st);
     P.dofs.build(n, 256, st);
-    P.fwd.clear();
-    P.bwd.clear();
-    P.fwd.resize(maxL);
-    P.bwd.resize(maxL);
-    for (int k = 0; k < maxL; ++k) {
-        std::vector<int64_t> rf(ns, 0), rb(ns, 0);
-        for (int i = 0; i < ns; ++i) {
-            const Layering &L = sys[i]->L;
-            if (k >= 1 && k < L.nlayers) rf[i] = L.bsize[k];
-            if (k <= L.nlayers - 2) rb[i] = L.bsize[k];
+    {
+        std::vector<int32_t> mp(1, 0), mm;
+        for (auto &v : members) {
+            mm.insert(mm.end(), v.begin(), v.end());
+            mp.push_back((int32_t)mm.size());
         }
-        P.fwd[k].build(rf, 4, st);
-        P.bwd[k].build(rb, 4, st);
+        P.memb_ptr.upload(mp, st);
+        P.memb.upload(mm, st);
     }
+    // cyclic-reduction phases: forward levels, last blocks, backward levels
+    int nlev = 0;
+    for (Factor *f : groups) nlev = std::max(nlev, (int)f->fwd.size());
+    auto task = [&](const Factor &f, const Factor::Blk &b, int g, int prec) {
+        (void)0;
+        BcrTask t{};
+        t.M = prec ? (const void *)(f.mat32.p + b.off) : (const void *)(f.mat.p + b.off);
+        t.rows = b.rows;
+        t.cols = b.cols;
+        t.nseg = b.nseg;
+        t.group = g;
+        for (int q = 0; q < SEGMAX; ++q) {
+            t.seg_len[q] = q < b.nseg ? f.bsize[b.seg_layer[q]] : 0;
+            t.seg_src[q] = q < b.nseg ? b.seg_src[q] : 0;
+            t.seg_off[q] = q < b.nseg ? f.boff[b.seg_layer[q]] : 0;
+        }
+        t.out_off = f.boff[b.layer];
+        t.out_dst = b.out_dst;
+        t.subtract = b.subtract;
+        const int nm = (int)members[g].size(), mc = bcr_mc(prec);
+        t.nmc = (nm + mc - 1) / mc;
+        return t;
+    };
+    P.phases.clear();
+    auto add_phase = [&](auto pick) {
+        std::vector<BcrTask> t64, t32;
+        std::vector<int64_t> u64, u32;
+        for (size_t g = 0; g < groups.size(); ++g)
+            for (const Factor::Blk *b : pick(*groups[g])) {
+                t64.push_back(task(*groups[g], *b, (int)g, 0));
+                t32.push_back(task(*groups[g], *b, (int)g, 1));
+                const int64_t rb = (b->rows + BCR_RB - 1) / BCR_RB;
+                u64.push_back(rb * t64.back().nmc);
+                u32.push_back(rb * t32.back().nmc);
+            }
+        if (t64.empty()) return;
+        P.phases.emplace_back();
+        PrecPhase &ph = P.phases.back();
+        ph.ntasks = (int)t64.size();
+        ph.tasks[0].upload(t64, st);
+        ph.tasks[1].upload(t32, st);
+        ph.sched[0].build(u64, 1, st);
+        ph.sched[1].build(u32, 1, st);
+    };
+    for (int lev = 0; lev < nlev; ++lev)
+        add_phase([&](const Factor &f) {
+            std::vector<const Factor::Blk *> v;
+            if (lev < (int)f.fwd.size())
+                for (const auto &b : f.fwd[lev]) v.push_back(&b);
+            return v;
+        });
+    add_phase([&](const Factor &f) {
+        std::vector<const Factor::Blk *> v;
+        for (const auto &b : f.tops) v.push_back(&b);
+        return v;
+    });
+    for (int lev = nlev - 1; lev >= 0; --lev)
+        add_phase([&](const Factor &f) {
+            std::vector<const Factor::Blk *> v;
+            if (lev < (int)f.bwd.size())
+                for (const auto &b : f.bwd[lev]) v.push_back(&b);
+            return v;
+        });
     x64.alloc(K.B.Ltot);
     b64.alloc(K.B.Ltot);
     r64.alloc(K.B.Ltot);
@@ -475,6 +421,7 @@ void Ctx::solve(const thm_solve_opts &o, float csign, const int32_t *mask, std::
     gp.max_iter = o.max_iter;
     gp.orth = o.orth;
     gp.use_graph = o.use_graph != 0;
+    gp.cplx = o.krylov == THM_KRYLOV_COMPLEX ? 1 : 0;
     if (o.precision == THM_FP64) {
         gmres_run<double>(K, ops64(csign), b64.p, x64.p, mask, gp, st);
         THM_HIP(hipMemcpyAsync(hi.data(), K.iters.p, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, st));
@@ -492,8 +439,11 @@ void Ctx::solve(const thm_solve_opts &o, float csign, const int32_t *mask, std::
     launch_norm2<double>(K.B, mask, b64.p, K.part.p, st);
     launch_norm_finish(K.B, K.part.p, mask, bnorm64.p, nullptr, 0.0, nullptr, nullptr, st);
     THM_HIP(hipMemcpyAsync(run_ir.p, mask, sizeof(int32_t) * ns, hipMemcpyDeviceToDevice, st));
+    // FP32 inner solves: one GMRES cycle each (stopped by the FP64 Givens estimate);
+    // accuracy comes from the FP64 refinement loop, not from the FP32 residual.
     GmresParams ip = gp;
     ip.rtol = o.ir_inner_rtol;
+    ip.max_iter = std::min(o.max_iter, K.m);
     for (int it = 0;; ++it) {
         A64.apply(x64.p, r64.p, b64.p, run_ir.p);
         launch_norm2<double>(K.B, run_ir.p, r64.p, K.part.p, st);
@@ -503,8 +453,17 @@ void Ctx::solve(const thm_solve_opts &o, float csign, const int32_t *mask, std::
         bool any = false;
         for (int i = 0; i < ns; ++i) any = any || hi[i];
         if (!any || it >= o.max_refine) break;
+        double worst = 0.0;
+        THM_HIP(hipMemcpyAsync(hr.data(), resid64.p, sizeof(double) * ns, hipMemcpyDeviceToHost, st));
+        THM_HIP(hipStreamSynchronize(st));
         for (int i = 0; i < ns; ++i)
-            if (hi[i]) refines[i]++;
+            if (hi[i]) {
+                refines[i]++;
+                worst = std::max(worst, hr[i]);
+            }
+        // the inner FP32 solve only has to gain the remaining factor (with margin),
+        // but never goes below what FP32 Arnoldi resolves
+        ip.rtol = std::max(o.ir_inner_rtol, 0.3 * o.rtol / std::max(worst, 1e-300));
         launch_scale<double, float>(K.B, run_ir.p, rnorm.p, 1, r64.p, b32.p, nullptr, 0, nullptr, st);
         THM_HIP(hipMemsetAsync(x32.p, 0, sizeof(float) * x32.n, st));
         gmres_run<float>(K, A32, b32.p, x32.p, run_ir.p, ip, st);

@@ -2,11 +2,43 @@
 // the per-call batched solve context.
 #pragma once
 #include <functional>
+#include <map>
+#include <memory>
 
 #include "kernels.h"
 
 namespace thm {
 struct Ddm;
+
+// Exact factorised K^{-1} (condensation + block cyclic reduction), shareable by
+// systems with identical matrices.
+struct Factor {
+    int nlayers = 0;
+    std::vector<int32_t> bsize;
+    std::vector<int64_t> boff;
+    int n_int = 0, ne = 0;
+    int64_t n_cells = 0;
+    DBuf<double> kiinv, F, mat;
+    DBuf<float> kiinv32, F32, mat32;
+    struct Blk {
+        int layer;
+        int64_t off;
+        int rows, cols, nseg;
+        int seg_layer[SEGMAX], seg_src[SEGMAX];
+        int out_dst, subtract;
+    };
+    std::vector<std::vector<Blk>> fwd, bwd;   // per level
+    std::vector<std::map<int, int>> fw_at, bk_at;
+    std::vector<std::vector<int>> level_pos;
+    // The reduction stops when few blocks remain; their block-tridiagonal system is
+    // inverted densely and applied as one phase (one task per block row).
+    std::vector<Blk> tops;
+    std::vector<int> top_pos;
+    int64_t top_off = 0;
+    int top_n = 0;
+    int64_t mat_elems = 0, bytes = 0;
+    double setup_ms = 0.0;
+};
 }
 
 // One assembled problem (global or one subdomain).  Owns all device memory.
@@ -35,13 +67,9 @@ struct thm_system {
     thm::DBuf<double> gD, rhs;  // complex, full length (2n doubles)
     thm::DBuf<int32_t> d2c_ptr, d2c_src;
 
-    // preconditioner (exact factorised K^{-1}, FP64 and FP32 copies)
-    bool prec_ready = false;
-    thm::DBuf<int32_t> Lskel_dof, Ldof_pos, Lcond_ptr, Lcond_cell, Lcond_loc, Lbsize;
-    thm::DBuf<int64_t> Lboff, Lsinv_off, Llf_off;
-    thm::DBuf<double> sinv, lf, lft, kiinv, F;
-    thm::DBuf<float> sinv32, lf32, lft32, kiinv32, F32;
-    double prec_setup_ms = 0.0;
+    // preconditioner: skeleton maps of this system and the (possibly shared) factor
+    thm::DBuf<int32_t> Lskel_dof, Ldof_pos, Lcond_ptr, Lcond_cell, Lcond_loc;
+    std::shared_ptr<thm::Factor> fac;
 
     // domain decomposition
     std::vector<std::unique_ptr<thm_system>> subs;
@@ -56,15 +84,18 @@ struct Krylov {
     Batch B;
     int m = 50;
     DBuf<double> H, cs, sn, g, y, hcol, hcol2, hnext, bnorm, beta, resid, est, part;
+    DBuf<double> rtol_d;  // Arnoldi stopping tolerance, read by the (captured) finish kernel
+    double rtol_h = 0.0;  // host copy (source of the async upload; lives with the workspace)
     DBuf<int32_t> running, active, jcnt, iters;
     DBuf<double> V64, w64, z64, cur64;
     DBuf<float> V32, w32, z32, cur32;
-    int32_t *pinned = nullptr;  // 2 x ns host flags
-    hipEvent_t ev[2] = {nullptr, nullptr};
+    static constexpr int NEV = 8;
+    int32_t *pinned = nullptr;  // NEV x ns host flags
+    hipEvent_t ev[NEV] = {};
     struct GraphSlot {
         hipGraphExec_t exec = nullptr;
         hipGraph_t graph = nullptr;
-        int key_T = -1, orth = -1, max_iter = -1;
+        int key_T = -1, orth = -1, max_iter = -1, cplx = -1;
         float csign = 0.f;
         double rtol = -1.0;
         const void *owner = nullptr;
@@ -95,6 +126,7 @@ struct GmresParams {
     int max_iter = 5000;
     int orth = THM_ORTH_CGS;
     bool use_graph = true;
+    int cplx = 1;  // complex-scalar Arnoldi (1) or real-scalar (0)
 };
 
 template <class T>
@@ -128,7 +160,7 @@ struct Ctx {
     void copy_out(int s, const double *slot, double *dst_dev);
 };
 
-void setup_precond(const std::vector<thm_system *> &systems, hipStream_t st);
+void setup_precond(const std::vector<thm_system *> &systems, hipStream_t st, bool share = true);
 double now_ms();
 
 }  // namespace thm

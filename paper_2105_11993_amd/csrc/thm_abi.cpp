@@ -4,6 +4,8 @@
 // catches, stores a thread-local message and returns a thm_status.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -281,6 +283,11 @@ static void assemble_system(thm_system &S, const thm_problem &p, uint32_t iface_
     build_side_csr(t, S.sides_c, S.C);
     build_side_csr(t, S.sides_inc, S.Minc);
     build_layering(t, S.dir, S.L);
+    S.Lskel_dof.upload(S.L.skel_dof, st);
+    S.Ldof_pos.upload(S.L.dof_pos, st);
+    S.Lcond_ptr.upload(S.L.cond_ptr, st);
+    S.Lcond_cell.upload(S.L.cond_cell, st);
+    S.Lcond_loc.upload(S.L.cond_loc, st);
     {
         std::vector<int64_t> key((size_t)t.n_cells * nl);
         std::vector<int32_t> val(key.size());
@@ -362,6 +369,7 @@ static void assemble_system(thm_system &S, const thm_problem &p, uint32_t iface_
 // ---------------------------------------------------------------- DDM construction
 static void build_ddm(thm_system &G, hipStream_t st) {
     const thm_problem &p = G.prob;
+    if (std::getenv("THM_PROGRESS")) std::fprintf(stderr, "[thm] building subdomain systems\n");
     const int d = p.dim;
     auto D = std::make_unique<Ddm>();
     int S[3] = {1, 1, 1}, nloc[3] = {1, 1, 1};
@@ -566,7 +574,7 @@ static void build_ddm(thm_system &G, hipStream_t st) {
     D->gdir.upload(std::vector<const uint8_t *>{G.dir_d.p}, st);
     D->gres.alloc(2 * G.n);
     D->gr2.alloc(2 * G.n);
-    D->gpart.alloc((size_t)std::max(1, D->Bg.vs.nblocks) * D->Bg.maxcols);
+    D->gpart.alloc((size_t)std::max(1, D->Bg.vs.nblocks) * NPW * D->Bg.maxcols);
     D->gnorm.alloc(2);
     D->Eg.alloc(2 * G.n);
     D->minus1.upload(std::vector<double>{-1.0}, st);
@@ -671,6 +679,8 @@ struct DdmRun {
 
 static void ddm_prepare(thm_system &G, const thm_solve_opts &o, bool batched, hipStream_t st) {
     Ddm &D = *G.ddm;
+    if (std::getenv("THM_PROGRESS"))
+        std::fprintf(stderr, "[thm] ddm prepare (%s, %d subdomains)\n", batched ? "batched" : "sequential", D.nsub);
     std::vector<thm_system *> subs;
     for (auto &s : G.subs) subs.push_back(s.get());
     if (batched) {
@@ -691,7 +701,7 @@ static void ddm_prepare(thm_system &G, const thm_solve_opts &o, bool batched, hi
         }
     } else if (D.singles.empty() || D.singles[0]->K.m != o.restart) {
         D.singles.clear();
-        setup_precond(subs, st);
+        setup_precond(subs, st, o.batched != 0);
         std::vector<double *> xs, bs;
         for (int s = 0; s < D.nsub; ++s) {
             auto c = std::make_unique<Ctx>();
@@ -721,7 +731,7 @@ static void ddm_solve_impl(thm_system &G, const thm_solve_opts &o, double *E, th
     ddm_prepare(G, o, batched, st);
     Ddm &D = *G.ddm;
     double setup = 0.0;
-    for (auto &s : G.subs) setup = std::max(setup, s->prec_setup_ms);
+    for (auto &s : G.subs) setup = std::max(setup, s->fac ? s->fac->setup_ms : 0.0);
     const double t1 = now_ms();
     thm_solve_opts io = o;
     io.rtol = o.inner_rtol;
@@ -752,8 +762,13 @@ static void ddm_solve_impl(thm_system &G, const thm_solve_opts &o, double *E, th
         run.update(D.tmp.p, 0, D.Gb.p);
         THM_HIP(hipMemsetAsync(D.G.p, 0, sizeof(double) * m2, st));
         KOps<double> ops;
+        const bool progress = std::getenv("THM_PROGRESS") != nullptr;
+        int napply = 0;
         ops.apply = [&](const double *x, double *y, const double *b, const int32_t *) {
             THM_HIP(hipStreamSynchronize(st));
+            if (progress && (++napply % 10) == 0)
+                std::fprintf(stderr, "[thm] ddm outer apply %d, inner iterations so far %d, %.1f ms\n", napply,
+                             run.sweeps_inner_iters, now_ms() - t1);
             run.inner_solve(x, false);
             run.update(x, 1, b ? D.tmp.p : y);
             if (b) {
@@ -770,6 +785,7 @@ static void ddm_solve_impl(thm_system &G, const thm_solve_opts &o, double *E, th
         gp.rtol = o.rtol;
         gp.orth = o.orth;
         gp.use_graph = false;
+        gp.cplx = o.krylov == THM_KRYLOV_COMPLEX ? 1 : 0;
         int budget = o.max_outer;
         for (int attempt = 0; attempt < 4 && budget > 0; ++attempt) {
             gp.max_iter = budget;
@@ -813,8 +829,9 @@ void thm_default_opts(thm_solve_opts *o) {
     o->outer_restart = 200;
     o->batched = 1;
     o->use_graph = 1;
-    o->ir_inner_rtol = 1e-5;
+    o->ir_inner_rtol = 1e-6;
     o->max_refine = 30;
+    o->krylov = THM_KRYLOV_COMPLEX;
 }
 
 const char *thm_last_error(void) { return g_last_error.c_str(); }
@@ -826,6 +843,7 @@ static void check_opts(const thm_solve_opts *o) {
     if (!(o->rtol >= 0.0)) fail(THM_EINVAL, "rtol must be >= 0");
     if (o->precision != THM_FP64 && o->precision != THM_FP32_IR) fail(THM_EINVAL, "unknown precision");
     if (o->orth != THM_ORTH_CGS && o->orth != THM_ORTH_CGS2) fail(THM_EINVAL, "unknown orthogonalisation");
+    if (o->krylov != THM_KRYLOV_COMPLEX && o->krylov != THM_KRYLOV_REAL) fail(THM_EINVAL, "unknown krylov kind");
 }
 
 thm_status thm_assemble(const thm_problem *p, void *stream, thm_system **out) {
@@ -889,7 +907,7 @@ thm_status thm_gmres_solve(int32_t nsys, thm_system *const *sys, const thm_solve
                 o.refinements = rf[s];
                 o.rel_residual = rs[s];
                 o.status = (rs[s] <= opts->rtol) ? THM_OK : THM_NOT_CONVERGED;
-                o.setup_ms = grp[s]->prec_setup_ms + (t1 - t0);
+                o.setup_ms = (grp[s]->fac ? grp[s]->fac->setup_ms : 0.0) + (t1 - t0);
                 o.solve_ms = t2 - t1;
                 worst = std::max(worst, (int)o.status);
             }
@@ -958,10 +976,7 @@ thm_status thm_system_info(const thm_system *sys, thm_info *info) {
         info->n_cells = sys->topo.n_cells;
         info->n_subdomains = sys->prob.subdomains[0] * sys->prob.subdomains[1] * sys->prob.subdomains[2];
         info->n_layers = sys->L.nlayers;
-        int64_t fb = sys->L.sinv_total + 2 * sys->L.lf_total;
-        const int ne = sys->topo.n_loc - sys->topo.n_int;
-        fb += sys->topo.n_cells * (int64_t)(sys->topo.n_int * sys->topo.n_int + ne * sys->topo.n_int);
-        info->factor_bytes = 8 * fb;
+        info->factor_bytes = sys->fac ? sys->fac->bytes : -1;
         info->n_interface = sys->ddm ? sys->ddm->nent : -1;
     });
 }
@@ -982,10 +997,8 @@ thm_status thm_system_set_mu(thm_system *sys, const double *mu_dev, void *stream
         THM_HIP(hipMemcpyAsync(sys->mu_d.p, mu_dev, sizeof(double) * h.size(), hipMemcpyDeviceToDevice, st));
         assemble_K(*sys, st);
         compute_lift(*sys, st);
-        sys->prec_ready = false;
-        if (sys->ddm) {
-            for (auto &s : sys->subs) s->prec_ready = false;
-        }
+        sys->fac.reset();
+        for (auto &s : sys->subs) s->fac.reset();
         THM_HIP(hipStreamSynchronize(st));
     });
 }

@@ -1,0 +1,147 @@
+"""GPU parity of the domain decomposition (eqs. (5)-(10)) and of the adjoint gradient."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import adjoint, ddm, system
+from tests._gpu_helpers import problem, rel, spec
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def thm():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2105_11993_amd as t
+    return t
+
+
+def _ddm_case(dim, m, p, S, omega, seed):
+    rng = np.random.default_rng(seed)
+    th = 0.3
+    return spec(dim, m, p, omega, mu=rng.uniform(1, 2, m ** dim), subdomains=S,
+                inc_dir=(np.cos(th), np.sin(th), 0.0), inc_pol=(-np.sin(th), np.cos(th), 0.0))
+
+
+DDM_CASES = [(2, 8, 1, (2, 2, 1), 6.0), (2, 12, 0, (3, 2, 1), 9.0), (2, 8, 2, (2, 2, 1), 8.0),
+             (3, 4, 0, (2, 2, 2), 4.0), (3, 4, 1, (2, 1, 1), 5.0)]
+
+
+@pytest.mark.parametrize("case", DDM_CASES, ids=lambda c: f"d{c[0]}m{c[1]}p{c[2]}")
+def test_ddm_jacobi_iterates_match_oracle(thm, case):
+    d = _ddm_case(*case, seed=7)
+    print("case", case, flush=True)
+    S = thm.thm_assemble(d)
+    D = ddm.DDM(problem(d))
+    ref, _ = D.jacobi(3)
+    for k in (1, 2, 3):
+        o = thm.default_opts(ddm_outer=thm.THM_DDM_JACOBI, max_outer=k, rtol=0.0, inner_rtol=1e-13)
+        E, st = thm.thm_ddm_solve(S, o)
+        assert st["outer_iters"] == k
+        assert rel(E.cpu().numpy(), ref[k - 1]) <= 1e-10, k
+
+
+@pytest.mark.parametrize("case", DDM_CASES, ids=lambda c: f"d{c[0]}m{c[1]}p{c[2]}")
+def test_ddm_gmres_reaches_global_solution(thm, case):
+    d = _ddm_case(*case, seed=8)
+    print("case", case, flush=True)
+    S = thm.thm_assemble(d)
+    Eg = system.solve_lu(system.assemble(problem(d)))
+    o = thm.default_opts(rtol=1e-12, inner_rtol=1e-13)
+    E, st = thm.thm_ddm_solve(S, o)
+    assert st["status"] == 0 and st["rel_residual"] <= 1e-12
+    assert rel(E.cpu().numpy(), Eg) <= 1e-10
+    o = thm.default_opts(rtol=1e-12, inner_rtol=1e-13, batched=0, use_graph=0)
+    E2, st2 = thm.thm_ddm_solve(S, o)
+    assert rel(E2.cpu().numpy(), Eg) <= 1e-10
+    o = thm.default_opts(rtol=1e-10, inner_rtol=1e-11, precision=thm.THM_FP32_IR)
+    E3, st3 = thm.thm_ddm_solve(S, o)
+    assert rel(E3.cpu().numpy(), Eg) <= 1e-8
+
+
+def test_ddm_single_subdomain_equals_single_domain(thm):
+    d = workloads.c1()
+    S = thm.thm_assemble(d)
+    Eg = system.solve_lu(system.assemble(problem(d)))
+    E, st = thm.thm_ddm_solve(S, thm.default_opts(rtol=1e-12, inner_rtol=1e-13))
+    assert rel(E.cpu().numpy(), Eg) <= 1e-10
+
+
+def test_adjoint_gradient_matches_oracle_and_fd(thm):
+    import torch
+    d = workloads.c5(16)
+    print("case c5-16", flush=True)
+    S = thm.thm_assemble(d)
+    opts = thm.default_opts(rtol=1e-13)
+    (E,), _ = thm.thm_gmres_solve([S], opts)
+    lo, hi = workloads.C5_TARGET
+    g, J = thm.thm_adjoint_grad(S, E, lo, hi, opts)
+    so = system.assemble(problem(d))
+    Eo = system.solve_lu(so)
+    MT = adjoint.target_mass(so, lo, hi)
+    go, _ = adjoint.gradient(so, Eo, MT)
+    Jo = adjoint.objective(so, Eo, MT)
+    assert abs(J - Jo) <= 1e-10 * abs(Jo)
+    assert rel(g.cpu().numpy(), go) <= 1e-8
+    cells = workloads.fd_cells(so.mesh.n_cells, 8)
+    fd = adjoint.fd_gradient(problem(d), cells, lo, hi)
+    gc = g.cpu().numpy()[cells]
+    assert (np.abs(gc - fd) / np.maximum(np.abs(fd), 1e-3 * np.abs(fd).max())).max() <= 1e-6
+
+
+def test_autograd_objective(thm):
+    import torch
+    d = workloads.c5(8)
+    S = thm.thm_assemble(d)
+    lo, hi = workloads.C5_TARGET
+    mu = torch.tensor(d["mu"], dtype=torch.float64, device="cuda", requires_grad=True)
+    J = thm.ThmObjective().apply(mu, S, lo, hi, thm.default_opts(rtol=1e-13))
+    J.backward()
+    so = system.assemble(problem(d))
+    Eo = system.solve_lu(so)
+    MT = adjoint.target_mass(so, lo, hi)
+    go, _ = adjoint.gradient(so, Eo, MT)
+    assert abs(J.item() - adjoint.objective(so, Eo, MT)) <= 1e-10 * abs(J.item())
+    assert rel(mu.grad.cpu().numpy(), go) <= 1e-8
+    # a second evaluation at a different mu re-assembles and re-factorises
+    mu2 = (mu.detach() * 1.1).requires_grad_(True)
+    J2 = thm.ThmObjective().apply(mu2, S, lo, hi, thm.default_opts(rtol=1e-13))
+    d2 = dict(d, mu=mu2.detach().cpu().numpy())
+    so2 = system.assemble(problem(d2))
+    E2 = system.solve_lu(so2)
+    assert abs(J2.item() - adjoint.objective(so2, E2, adjoint.target_mass(so2, lo, hi))) <= 1e-10 * abs(J2.item())
+
+
+def test_failure_paths(thm):
+    d = workloads.c1()
+    bad = dict(d, mu=-np.ones(256))
+    with pytest.raises(thm.ThmError) as e:
+        thm.thm_assemble(bad)
+    assert e.value.code == -1
+    with pytest.raises(thm.ThmError) as e:
+        thm.thm_assemble(dict(d, inc_faces=0b1111))
+    assert e.value.code == -1
+    S = thm.thm_assemble(d)
+    (E,), (st,) = thm.thm_gmres_solve([S], thm.default_opts(max_iter=3), allow_not_converged=True)
+    assert st["status"] == 1 and st["iters"] <= 3
+    # zero incident field -> zero solution after zero iterations
+    Z = thm.thm_assemble(dict(d, inc_pol=(0.0, 0.0, 0.0)))
+    (E,), (st,) = thm.thm_gmres_solve([Z], thm.default_opts())
+    assert st["iters"] == 0 and float(E.abs().max()) == 0.0
+
+
+def test_ddm_shared_factors_homogeneous_partition(thm):
+    """4x4 partition of a homogeneous square: subdomains off the x = 0 side share one factor."""
+    d = dict(workloads.c2(32))
+    print("case c2-32", flush=True)
+    S = thm.thm_assemble(d)
+    Eg = system.solve_lu(system.assemble(problem(d)))
+    for prec in (thm.THM_FP64, thm.THM_FP32_IR):
+        o = thm.default_opts(rtol=1e-11, inner_rtol=1e-12, restart=80, precision=prec)
+        E, st = thm.thm_ddm_solve(S, o)
+        assert st["rel_residual"] <= 1e-11
+        assert rel(E.cpu().numpy(), Eg) <= (1e-9 if prec == thm.THM_FP64 else 1e-8)
+    o = thm.default_opts(rtol=1e-10, inner_rtol=1e-11, krylov=thm.THM_KRYLOV_REAL, restart=80)
+    E, st = thm.thm_ddm_solve(S, o)
+    assert rel(E.cpu().numpy(), Eg) <= 1e-8
