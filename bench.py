@@ -154,11 +154,19 @@ def main():
     for name, prec in (("fp64", thm.THM_FP64), ("fp32", thm.THM_FP32_IR)):
         ms, by = thm.thm_time_spmv(S, prec, reps=50)
         spmv[name] = {"ms": ms, "bytes": by, "GBps": by / ms / 1e6}
+    spmv["variant_fp64"] = S.fresh_info()["spmv_variant"]
     log(args, f"spmv: {spmv}")
+    # dominant kernel of the timed solve: the cyclic-reduction multi-GEMV of the batched
+    # FP32 subdomain preconditioner (HIP events on the library stream, same launches as
+    # inside the solve)
+    ms, by, nl = thm.thm_time_precond(S, thm.THM_FP32_IR, reps=20)
     peak = 8000.0
-    roof = {"bound": "hbm", "kernel": "k_spmv<8,double> (global 2x2 block operator, FP64)",
-            "achieved": spmv["fp64"]["GBps"], "peak": peak, "unit": "GB/s",
-            "frac": spmv["fp64"]["GBps"] / peak, "traffic": None}
+    ach = by / ms / 1e6
+    roof = {"bound": "hbm", "kernel": "k_bcr_gemv<float> (batched FP32 cyclic-reduction multi-GEMV, 16 subdomains, "
+                                      "2 shared factors)",
+            "achieved": ach, "peak": peak, "unit": "GB/s", "frac": ach / peak, "traffic": None,
+            "launches_per_apply": nl, "avg_launch_us": ms / nl * 1e3, "bytes_per_apply": by}
+    log(args, f"roofline: {roof}")
 
     st = stats[len(stats) // 2]
     out = {

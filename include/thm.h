@@ -110,7 +110,10 @@ typedef struct {
     int32_t n_subdomains;
     int32_t n_layers;        /* block-tridiagonal preconditioner layers */
     int64_t factor_bytes;    /* FP64 preconditioner storage */
-    int64_t n_interface;     /* complex interface unknowns of the DDM (sum over directed interfaces) */
+    int64_t n_interface;     /* complex interface unknowns of the DDM (sum over directed interfaces; -1 before
+                                the first DDM solve) */
+    int32_t spmv_variant;    /* autotuned FP64 SpMV variant of this system's context (10 x lanes per row +
+                                unroll), -1 before the first solve */
 } thm_info;
 
 typedef struct thm_system thm_system;
@@ -195,6 +198,14 @@ thm_status thm_export_elements(thm_system *sys, int64_t c0, int64_t count, doubl
  * measured with HIP events on `stream`; bytes_out: algorithmic bytes per launch. */
 thm_status thm_time_spmv(thm_system *sys, int32_t precision, int32_t reps, double *ms_out,
                          double *bytes_out, void *stream);
+
+/* Average device time (ms) of `reps` applications of the block cyclic-reduction
+ * phases of the preconditioner (eq. (11)) -- the DDM's batched subdomain context if a
+ * DDM solve has run on `sys`, else the system's own -- measured with HIP events on the
+ * library's stream.  bytes_out: algorithmic bytes per application (every factor matrix
+ * once plus member vectors); launches_out: kernel launches per application. */
+thm_status thm_time_precond(thm_system *sys, int32_t precision, int32_t reps, double *ms_out, double *bytes_out,
+                            int32_t *launches_out, void *stream);
 
 #ifdef __cplusplus
 }

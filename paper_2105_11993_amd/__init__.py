@@ -53,17 +53,19 @@ class ThmStats(ctypes.Structure):
 class ThmInfo(ctypes.Structure):
     _fields_ = [("n_dofs", ctypes.c_int64), ("n_free", ctypes.c_int64), ("nnz", ctypes.c_int64),
                 ("nnz_c", ctypes.c_int64), ("n_cells", ctypes.c_int64), ("n_subdomains", ctypes.c_int32),
-                ("n_layers", ctypes.c_int32), ("factor_bytes", ctypes.c_int64), ("n_interface", ctypes.c_int64)]
+                ("n_layers", ctypes.c_int32), ("factor_bytes", ctypes.c_int64), ("n_interface", ctypes.c_int64),
+                ("spmv_variant", ctypes.c_int32)]
 
 
 EXPORTS = ["thm_default_opts", "thm_assemble", "thm_gmres_solve", "thm_ddm_solve", "thm_adjoint_grad",
            "thm_system_info", "thm_system_set_mu", "thm_system_destroy", "thm_last_error", "thm_apply_operator",
-           "thm_apply_precond", "thm_export_matrices", "thm_export_rhs", "thm_export_elements", "thm_time_spmv"]
+           "thm_apply_precond", "thm_export_matrices", "thm_export_rhs", "thm_export_elements", "thm_time_spmv",
+           "thm_time_precond"]
 
 
 def load_library(path=LIB_PATH):
     if not os.path.exists(path):
-        raise ImportError(f"{path} is not built; run `python -m paper_2105_11993_amd.build_lib`")
+        raise ImportError(f"{path} is not built; run `python paper_2105_11993_amd/build_lib.py`")
     lib = ctypes.CDLL(path)
     vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)
     sig = {
@@ -83,6 +85,7 @@ def load_library(path=LIB_PATH):
         "thm_export_rhs": (i32, [vp, vp, vp, vp]),
         "thm_export_elements": (i32, [vp, i64, i64, vp]),
         "thm_time_spmv": (i32, [vp, i32, i32, dp, dp, vp]),
+        "thm_time_precond": (i32, [vp, i32, i32, dp, dp, ctypes.POINTER(i32), vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -170,10 +173,13 @@ class System:
     @property
     def info(self):
         if self._info is None:
-            i = ThmInfo()
-            _check(_lib.thm_system_info(self.handle, ctypes.byref(i)))
-            self._info = {k: getattr(i, k) for k, _ in ThmInfo._fields_}
+            self._info = self.fresh_info()
         return self._info
+
+    def fresh_info(self):
+        i = ThmInfo()
+        _check(_lib.thm_system_info(self.handle, ctypes.byref(i)))
+        return {k: getattr(i, k) for k, _ in ThmInfo._fields_}
 
     @property
     def n(self):
@@ -305,6 +311,16 @@ def thm_time_spmv(system, precision=THM_FP64, reps=20, stream=None):
     _check(_lib.thm_time_spmv(system.handle, int(precision), int(reps), ctypes.byref(ms), ctypes.byref(by),
                               _stream(stream)))
     return ms.value, by.value
+
+
+def thm_time_precond(system, precision=THM_FP64, reps=20, stream=None):
+    """(ms per application, algorithmic bytes per application, launches per application)."""
+    ms = ctypes.c_double()
+    by = ctypes.c_double()
+    nl = ctypes.c_int32()
+    _check(_lib.thm_time_precond(system.handle, int(precision), int(reps), ctypes.byref(ms), ctypes.byref(by),
+                                 ctypes.byref(nl), _stream(stream)))
+    return ms.value, by.value, nl.value
 
 
 def _make_objective():

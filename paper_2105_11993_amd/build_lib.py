@@ -1,6 +1,7 @@
 """Build libthm.so (HIP, gfx950) in-tree.
 
-Usage: python -m paper_2105_11993_amd.build_lib [--jobs N]
+Usage: python paper_2105_11993_amd/build_lib.py [--jobs N]
+(run by path: importing the package requires the built library)
 Compiles every source under csrc/ with hipcc for gfx950 into _build/ and links
 paper_2105_11993_amd/libthm.so.
 """

@@ -18,15 +18,22 @@ struct MatDesc {
 };
 
 // Flattened block schedule: block b belongs to system s with blkoff[s] <= b < blkoff[s+1].
+// The device array holds blkoff[0..ns] followed by the block -> system map, so a kernel
+// finds its system with one load: blkoff[ns + 1 + b].
 struct Sched {
     DBuf<int32_t> blkoff;
     std::vector<int32_t> h;
     int nblocks = 0;
     void build(const std::vector<int64_t> &units, int64_t per_block, hipStream_t st) {
-        h.assign(units.size() + 1, 0);
-        for (size_t s = 0; s < units.size(); ++s) h[s + 1] = h[s] + (int32_t)((units[s] + per_block - 1) / per_block);
+        const size_t ns = units.size();
+        h.assign(ns + 1, 0);
+        for (size_t s = 0; s < ns; ++s) h[s + 1] = h[s] + (int32_t)((units[s] + per_block - 1) / per_block);
         nblocks = h.back();
-        blkoff.upload(h, st);
+        std::vector<int32_t> all(h);
+        all.reserve(ns + 1 + nblocks);
+        for (size_t s = 0; s < ns; ++s)
+            for (int32_t b = h[s]; b < h[s + 1]; ++b) all.push_back((int32_t)s);
+        blkoff.upload(all, st);
     }
 };
 
@@ -39,7 +46,7 @@ struct Batch {
     int64_t Ltot = 0;                  // scalars per vector slot
     Sched vs;                          // VCHUNK scalars per block
     Sched es;                          // 256 complex entries per block
-    std::map<int, Sched> spmv;         // rows per block = 256 / lpr
+    std::map<int, Sched> spmv;         // per SpMV variant (10 * lanes_per_row + unroll): 256 / lpr rows per block
     void init(const std::vector<int64_t> &n, int maxcols_, hipStream_t st) {
         ns = (int)n.size();
         maxcols = maxcols_;
@@ -64,7 +71,7 @@ struct Batch {
         auto it = spmv.find(lpr);
         if (it != spmv.end()) return it->second;
         Sched &sc = spmv[lpr];
-        sc.build(h_nvec, 256 / lpr, st);
+        sc.build(h_nvec, 256 / (lpr / 10), st);
         return sc;
     }
 };
@@ -150,6 +157,8 @@ struct PrecBatch {
     std::vector<PrecPhase> phases; // forward levels, top, backward levels
 };
 
+template <class T>
+void launch_bcr_phases(const PrecBatch &P, const int32_t *mask, T *ws, T *ys, hipStream_t st);
 template <class T>
 void launch_prec_apply(const PrecBatch &P, const PrecDesc *d, const int64_t *off, int ns, const int32_t *mask,
                        const T *r, T *x, T *ws, T *ys, hipStream_t st);

@@ -14,12 +14,7 @@ namespace thm {
 
 // ------------------------------------------------------------------ helpers
 __device__ __forceinline__ int find_sys(const int32_t *blkoff, int ns, int b) {
-    int lo = 0, hi = ns;  // blkoff[lo] <= b < blkoff[hi]
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (blkoff[mid] <= b) lo = mid; else hi = mid;
-    }
-    return lo;
+    return blkoff[ns + 1 + b];  // block -> system map stored after the offsets
 }
 
 template <class T>
@@ -48,7 +43,7 @@ template <> struct V2<float> { using t = float2; };
 // ------------------------------------------------------------------ SpMV
 // y = A x  or  y = b - A x, A = [[K, -sC], [sC, K]] acting on interleaved (re, im)
 // pairs, s = +1 (A) or -1 (A^T).  K is read once for both halves.  LPR lanes per row.
-template <int LPR, class T>
+template <int LPR, int UNR, class T>
 __global__ void __launch_bounds__(256) k_spmv(const MatDesc *__restrict__ mats, const int64_t *__restrict__ off,
                                               const int32_t *__restrict__ blkoff, int ns,
                                               const int32_t *__restrict__ mask, const T *__restrict__ xb,
@@ -65,7 +60,27 @@ __global__ void __launch_bounds__(256) k_spmv(const MatDesc *__restrict__ mats, 
     const T *kv = reinterpret_cast<const T *>(m.kval);
     T ar = 0, ai = 0;
     const int32_t r0 = m.rowptr[row], r1 = m.rowptr[row + 1];
-    for (int32_t q = r0 + lane; q < r1; q += LPR) {
+    // UNR entries per lane are loaded before the FMAs (memory-level parallelism).
+    int32_t q = r0 + lane;
+    if (UNR > 1)
+        for (; q + (UNR - 1) * LPR < r1; q += UNR * LPR) {
+            T k[UNR];
+            int32_t c[UNR];
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+                k[u] = kv[q + u * LPR];
+                c[u] = m.col[q + u * LPR];
+            }
+            T2 xv[UNR];
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) xv[u] = x[c[u]];
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+                ar += k[u] * xv[u].x;
+                ai += k[u] * xv[u].y;
+            }
+        }
+    for (; q < r1; q += LPR) {
         const T k = kv[q];
         const T2 xv = x[m.col[q]];
         ar += k * xv.x;
@@ -95,19 +110,20 @@ __global__ void __launch_bounds__(256) k_spmv(const MatDesc *__restrict__ mats, 
     }
 }
 
+// Variant code v = 10 * lanes_per_row + unroll (unroll 1 or 4), chosen by the autotuner.
 template <class T>
-void launch_spmv(int lpr, const MatDesc *mats, const int64_t *off, const Sched &sc, int ns, const int32_t *mask,
+void launch_spmv(int v, const MatDesc *mats, const int64_t *off, const Sched &sc, int ns, const int32_t *mask,
                  const T *x, T *y, const T *b, float csign, hipStream_t st) {
     if (!sc.nblocks) return;
     const dim3 g(sc.nblocks), blk(256);
-    switch (lpr) {
-        case 2: k_spmv<2, T><<<g, blk, 0, st>>>(mats, off, sc.blkoff.p, ns, mask, x, y, b, csign); break;
-        case 4: k_spmv<4, T><<<g, blk, 0, st>>>(mats, off, sc.blkoff.p, ns, mask, x, y, b, csign); break;
-        case 8: k_spmv<8, T><<<g, blk, 0, st>>>(mats, off, sc.blkoff.p, ns, mask, x, y, b, csign); break;
-        case 16: k_spmv<16, T><<<g, blk, 0, st>>>(mats, off, sc.blkoff.p, ns, mask, x, y, b, csign); break;
-        case 32: k_spmv<32, T><<<g, blk, 0, st>>>(mats, off, sc.blkoff.p, ns, mask, x, y, b, csign); break;
-        default: k_spmv<64, T><<<g, blk, 0, st>>>(mats, off, sc.blkoff.p, ns, mask, x, y, b, csign); break;
+#define SPMV_CASE(L, U) \
+    case 10 * L + U: k_spmv<L, U, T><<<g, blk, 0, st>>>(mats, off, sc.blkoff.p, ns, mask, x, y, b, csign); break;
+    switch (v) {
+        SPMV_CASE(2, 1) SPMV_CASE(4, 1) SPMV_CASE(8, 1) SPMV_CASE(16, 1) SPMV_CASE(32, 1) SPMV_CASE(64, 1)
+        SPMV_CASE(2, 4) SPMV_CASE(4, 4) SPMV_CASE(8, 4) SPMV_CASE(16, 4) SPMV_CASE(32, 4)
+        default: fail(THM_EINVAL, "unknown SpMV variant");
     }
+#undef SPMV_CASE
     THM_HIP(hipGetLastError());
 }
 template void launch_spmv<double>(int, const MatDesc *, const int64_t *, const Sched &, int, const int32_t *,

@@ -11,12 +11,7 @@
 namespace thm {
 
 __device__ __forceinline__ int find_sys2(const int32_t *blkoff, int ns, int b) {
-    int lo = 0, hi = ns;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (blkoff[mid] <= b) lo = mid; else hi = mid;
-    }
-    return lo;
+    return blkoff[ns + 1 + b];  // block -> system map stored after the offsets
 }
 
 template <class T> struct P2;
@@ -587,16 +582,24 @@ __global__ void __launch_bounds__(256) k_cond_bwd(const PrecDesc *__restrict__ p
 }
 
 template <class T>
-void launch_prec_apply(const PrecBatch &P, const PrecDesc *d, const int64_t *off, int ns, const int32_t *mask,
-                       const T *r, T *x, T *ws, T *ys, hipStream_t st) {
-    if (P.skel.nblocks)
-        k_cond_fwd<T><<<P.skel.nblocks, 256, 0, st>>>(d, off, P.soff.p, P.skel.blkoff.p, ns, mask, r, ws);
+void launch_bcr_phases(const PrecBatch &P, const int32_t *mask, T *ws, T *ys, hipStream_t st) {
     const int prec = sizeof(T) == 8 ? 0 : 1;
     for (const PrecPhase &ph : P.phases)
         if (ph.sched[prec].nblocks)
             k_bcr_gemv<T><<<ph.sched[prec].nblocks, 256, 0, st>>>(ph.tasks[prec].p, ph.sched[prec].blkoff.p,
                                                                    ph.ntasks, P.memb_ptr.p, P.memb.p, P.soff.p, mask,
                                                                    ws, ys);
+    THM_HIP(hipGetLastError());
+}
+template void launch_bcr_phases<double>(const PrecBatch &, const int32_t *, double *, double *, hipStream_t);
+template void launch_bcr_phases<float>(const PrecBatch &, const int32_t *, float *, float *, hipStream_t);
+
+template <class T>
+void launch_prec_apply(const PrecBatch &P, const PrecDesc *d, const int64_t *off, int ns, const int32_t *mask,
+                       const T *r, T *x, T *ws, T *ys, hipStream_t st) {
+    if (P.skel.nblocks)
+        k_cond_fwd<T><<<P.skel.nblocks, 256, 0, st>>>(d, off, P.soff.p, P.skel.blkoff.p, ns, mask, r, ws);
+    launch_bcr_phases<T>(P, mask, ws, ys, st);
     if (P.dofs.nblocks)
         k_cond_bwd<T><<<P.dofs.nblocks, 256, 0, st>>>(d, off, P.soff.p, P.dofs.blkoff.p, ns, mask, r, ys, x);
     THM_HIP(hipGetLastError());

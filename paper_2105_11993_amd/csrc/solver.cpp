@@ -310,6 +310,8 @@ void Ctx::build(const std::vector<thm_system *> &s, int m, hipStream_t stream) {
         return t;
     };
     P.phases.clear();
+    bcr_bytes[0].clear();
+    bcr_bytes[1].clear();
     auto add_phase = [&](auto pick) {
         std::vector<BcrTask> t64, t32;
         std::vector<int64_t> u64, u32;
@@ -322,6 +324,16 @@ void Ctx::build(const std::vector<thm_system *> &s, int m, hipStream_t stream) {
                 u32.push_back(rb * t32.back().nmc);
             }
         if (t64.empty()) return;
+        for (int prec = 0; prec < 2; ++prec) {
+            const double v = prec ? 4.0 : 8.0;
+            double by = 0.0;
+            const auto &tt = prec ? t32 : t64;
+            for (const BcrTask &t : tt) {
+                const double nm = (double)members[t.group].size();
+                by += (double)t.rows * t.cols * v + nm * 2.0 * v * (t.cols + t.rows * (t.subtract ? 2.0 : 1.0));
+            }
+            bcr_bytes[prec].push_back(by);
+        }
         P.phases.emplace_back();
         PrecPhase &ph = P.phases.back();
         ph.ntasks = (int)t64.size();
@@ -477,6 +489,31 @@ void Ctx::solve(const thm_solve_opts &o, float csign, const int32_t *mask, std::
     for (int i = 0; i < ns; ++i) resid[i] = hr[i];
 }
 
+double Ctx::time_bcr(int prec, int reps, double *bytes, int *launches) {
+    if (prec) ops32(1.f);
+    hipEvent_t e0, e1;
+    THM_HIP(hipEventCreate(&e0));
+    THM_HIP(hipEventCreate(&e1));
+    auto once = [&] {
+        if (prec) launch_bcr_phases<float>(P, nullptr, ws32.p, ys32.p, st);
+        else launch_bcr_phases<double>(P, nullptr, ws64.p, ys64.p, st);
+    };
+    once();
+    THM_HIP(hipEventRecord(e0, st));
+    for (int r = 0; r < reps; ++r) once();
+    THM_HIP(hipEventRecord(e1, st));
+    THM_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    THM_HIP(hipEventElapsedTime(&ms, e0, e1));
+    THM_HIP(hipEventDestroy(e0));
+    THM_HIP(hipEventDestroy(e1));
+    double by = 0.0;
+    for (double b : bcr_bytes[prec]) by += b;
+    if (bytes) *bytes = by;
+    if (launches) *launches = (int)P.phases.size();
+    return ms / reps;
+}
+
 void Ctx::copy_in(int s, const double *src, double *slot) {
     THM_HIP(hipMemcpyAsync(slot + K.B.h_off[s], src, sizeof(double) * 2 * sys[s]->n, hipMemcpyDeviceToDevice, st));
 }
@@ -512,7 +549,7 @@ static void tune_store() {
 }
 
 void Ctx::autotune() {
-    const int cand[] = {2, 4, 8, 16, 32};
+    const int cand[] = {21, 41, 81, 161, 321, 24, 44, 84, 164, 324};
     for (int c : cand) K.B.spmv_sched(c, st);
     int64_t nnz = 0, nrows = 0;
     for (thm_system *s : sys) {

@@ -146,7 +146,7 @@ struct Ctx {
     DBuf<float> x32, b32, ws32, ys32;
     DBuf<int32_t> mask_all, run_ir;
     DBuf<double> rnorm, bnorm64, resid64;
-    int lpr64 = 8, lpr32 = 8;
+    int lpr64 = 81, lpr32 = 81;  // SpMV variants (10 * lanes_per_row + unroll)
 
     void build(const std::vector<thm_system *> &s, int m, hipStream_t stream);
     KOps<double> ops64(float csign);
@@ -156,6 +156,11 @@ struct Ctx {
     void solve(const thm_solve_opts &o, float csign, const int32_t *mask, std::vector<int> &iters,
                std::vector<int> &refines, std::vector<double> &resid);
     void autotune();
+    // Time `reps` applications of the cyclic-reduction phases (k_bcr_gemv launches only)
+    // with HIP events on this context's stream; returns ms per application, and the
+    // algorithmic bytes and number of launches per application.
+    double time_bcr(int prec, int reps, double *bytes, int *launches);
+    std::vector<double> bcr_bytes[2];  // per phase, per precision (matrix once + member vectors)
     void copy_in(int s, const double *src_dev, double *slot);
     void copy_out(int s, const double *slot, double *dst_dev);
 };

@@ -204,7 +204,7 @@ static void project_dirichlet(thm_system &S, hipStream_t st) {
     MatDesc md{n, mrp.p, mcol.p, mval.p, zptr.p, zptr.p, mval.p};
     DBuf<MatDesc> mdd;
     mdd.upload(std::vector<MatDesc>{md}, st);
-    const Sched &sc8 = B1.spmv_sched(8, st);
+    const Sched &sc8 = B1.spmv_sched(81, st);
     const int64_t m2 = 2 * n;
     THM_HIP(hipMemsetAsync(S.gD.p, 0, sizeof(double) * m2, st));
     THM_HIP(hipMemcpyAsync(r.p, s.p, sizeof(double) * m2, hipMemcpyDeviceToDevice, st));
@@ -218,7 +218,7 @@ static void project_dirichlet(thm_system &S, hipStream_t st) {
     const double bn = std::sqrt(hs[5]);
     if (bn == 0.0) return;
     for (int it = 0; it < 1000; ++it) {
-        launch_spmv<double>(8, mdd.p, B1.off.p, sc8, 1, nullptr, p.p, q.p, nullptr, 0.f, st);
+        launch_spmv<double>(81, mdd.p, B1.off.p, sc8, 1, nullptr, p.p, q.p, nullptr, 0.f, st);
         launch_dot1(m2, p.p, q.p, sc.p + 1, st);
         launch_cg_step(m2, 0, sc.p, S.gD.p, p.p, r.p, q.p, nullptr, nullptr, st);
         launch_dot1(m2, r.p, r.p, sc.p + 4, st);
@@ -240,7 +240,7 @@ static void compute_lift(thm_system &S, hipStream_t st) {
     MatDesc md{S.n, S.k_rowptr.p, S.k_col.p, S.kraw.p, S.c_rowptr.p, S.c_col.p, S.craw.p};
     DBuf<MatDesc> mdd;
     mdd.upload(std::vector<MatDesc>{md}, st);
-    launch_spmv<double>(8, mdd.p, B1.off.p, B1.spmv_sched(8, st), 1, nullptr, S.gD.p, S.rhs.p, nullptr, 1.f, st);
+    launch_spmv<double>(81, mdd.p, B1.off.p, B1.spmv_sched(81, st), 1, nullptr, S.gD.p, S.rhs.p, nullptr, 1.f, st);
     launch_lift_finish(S.n, S.dir_d.p, S.rhs.p, st);
     THM_HIP(hipStreamSynchronize(st));
 }
@@ -579,7 +579,7 @@ static void build_ddm(thm_system &G, hipStream_t st) {
     D->Eg.alloc(2 * G.n);
     D->minus1.upload(std::vector<double>{-1.0}, st);
     D->one.upload(std::vector<int32_t>{1}, st);
-    D->Bg.spmv_sched(8, st);
+    D->Bg.spmv_sched(81, st);
     THM_HIP(hipStreamSynchronize(st));
     G.ddm = std::move(D);
 }
@@ -662,8 +662,8 @@ struct DdmRun {
         if (Eout) THM_HIP(hipMemcpyAsync(Eout, D.Eg.p, sizeof(double) * 2 * G.n, hipMemcpyDeviceToDevice, st));
         THM_HIP(hipMemcpyAsync(D.gres.p, D.Eg.p, sizeof(double) * 2 * G.n, hipMemcpyDeviceToDevice, st));
         launch_zero_flagged<double>(D.Bg, D.gdir.p, D.gres.p, st);
-        const Sched &sc = D.Bg.spmv_sched(8, st);
-        launch_spmv<double>(8, D.gmat.p, D.Bg.off.p, sc, 1, nullptr, D.gres.p, D.gr2.p, G.rhs.p, 1.f, st);
+        const Sched &sc = D.Bg.spmv_sched(81, st);
+        launch_spmv<double>(81, D.gmat.p, D.Bg.off.p, sc, 1, nullptr, D.gres.p, D.gr2.p, G.rhs.p, 1.f, st);
         launch_norm2<double>(D.Bg, nullptr, D.gr2.p, D.gpart.p, st);
         launch_norm_finish(D.Bg, D.gpart.p, nullptr, D.gnorm.p, nullptr, 0.0, nullptr, nullptr, st);
         launch_norm2<double>(D.Bg, nullptr, G.rhs.p, D.gpart.p, st);
@@ -978,6 +978,12 @@ thm_status thm_system_info(const thm_system *sys, thm_info *info) {
         info->n_layers = sys->L.nlayers;
         info->factor_bytes = sys->fac ? sys->fac->bytes : -1;
         info->n_interface = sys->ddm ? sys->ddm->nent : -1;
+        info->spmv_variant = -1;
+        {
+            std::lock_guard<std::mutex> lk(g_cache_mu);
+            auto it = g_ctx_cache.find(std::vector<thm_system *>{const_cast<thm_system *>(sys)});
+            if (it != g_ctx_cache.end() && it->second) info->spmv_variant = it->second->lpr64;
+        }
     });
 }
 
@@ -1126,6 +1132,24 @@ thm_status thm_time_spmv(thm_system *sys, int32_t precision, int32_t reps, doubl
         const double nnz = (double)sys->K.col.size() + (double)sys->C.col.size();
         if (bytes_out) *bytes_out = (v + 4.0) * nnz + 2.0 * 4.0 * (sys->n + 1) + 2.0 * 2.0 * sys->n * v;
         stream_join(c.st, us);
+    });
+}
+
+thm_status thm_time_precond(thm_system *sys, int32_t precision, int32_t reps, double *ms_out, double *bytes_out,
+                            int32_t *launches_out, void *stream) {
+    return guard([&] {
+        if (!sys || !ms_out || reps < 1) fail(THM_EINVAL, "bad arguments");
+        hipStream_t us = (hipStream_t)stream;
+        Ctx *c = nullptr;
+        if (sys->ddm && sys->ddm->inner) c = sys->ddm->inner.get();
+        else c = &get_ctx({sys}, 50);
+        stream_join(us, c->st);
+        double by = 0.0;
+        int nl = 0;
+        *ms_out = c->time_bcr(precision == THM_FP32_IR ? 1 : 0, reps, &by, &nl);
+        if (bytes_out) *bytes_out = by;
+        if (launches_out) *launches_out = nl;
+        stream_join(c->st, us);
     });
 }
 
