@@ -109,7 +109,7 @@ typedef struct {
     int64_t n_cells;
     int32_t n_subdomains;
     int32_t n_layers;        /* block-tridiagonal preconditioner layers */
-    int64_t factor_bytes;    /* FP64 preconditioner storage */
+    int64_t factor_bytes;    /* device bytes of the preconditioner factor (FP64 and FP32 copies) */
     int64_t n_interface;     /* complex interface unknowns of the DDM (sum over directed interfaces; -1 before
                                 the first DDM solve) */
     int32_t spmv_variant;    /* autotuned FP64 SpMV variant of this system's context (10 x lanes per row +

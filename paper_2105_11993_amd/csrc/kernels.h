@@ -118,27 +118,47 @@ struct PrecDesc {
     int64_t n;                 // complex DoFs
     int64_t n_skel;            // skeleton DoFs
     int64_t cell_off;          // first interior DoF
+    int64_t sp;                // planar half-stride of the skeleton work vectors (re block, then im block)
     int32_t n_cells, n_loc, n_int, ne, nlayers;
     const int32_t *cell_dofs;  // n_cells * n_loc
-    const int32_t *skel_dof, *dof_pos;
+    const int32_t *skel_dof;   // skeleton position -> global DoF
+    const int32_t *skel_pos;   // skeleton position -> padded position in the work vectors
+    const int32_t *dof_pos;    // global DoF -> padded position (-1: interior)
     const int32_t *cond_ptr, *cond_cell, *cond_loc;
     const void *kiinv, *F;         // double or float
 };
 
-// One multi-GEMV task of the cyclic-reduction application (see kernels_prec.hip).
-constexpr int SEGMAX = 16;  // input segments of one task (the dense last block reads all its positions)
+// One dense task of the cyclic-reduction application (see kernels_prec.hip): the
+// product of a rows x (padded) matrix with the concatenated input segments of every
+// member of a factor group.  Columns of segment q occupy [seg_pstart[q], seg_pstart[q+1]);
+// the part past the layer's true width is zero in the matrix and in the vectors.
+constexpr int SEGMAX = 16;   // input segments of one task (the dense last block reads all its positions)
+constexpr int BCR_KS = 32;   // columns per MFMA step (4 lane groups x 8 consecutive columns)
+constexpr int BCR_RT = 32;   // rows per block (two 16-row MFMA tiles)
+constexpr int BCR_NM = 16;   // members per block at most (two 16-wide n tiles, re and im columns)
 struct BcrTask {
-    const void *M;             // row-major rows x cols (double or float)
-    int32_t rows, cols, nseg, group;
-    int32_t seg_len[SEGMAX], seg_src[SEGMAX];  // seg_src: 0 = ws (reduced RHS), 1 = ys (solution)
-    int64_t seg_off[SEGMAX];   // complex offset of the segment inside a member's skeleton vector
-    int64_t out_off;           // complex offset of the output block
+    const void *M;             // row-major rows x ld (double or float), 16-byte aligned rows
+    int32_t rows, ld, nseg, group;
+    int32_t kq;                // columns per wave (multiple of BCR_KS)
+    int32_t nnt;               // 16-wide n tiles per block (1 or 2): members per block = 8 nnt
+    int32_t nmc;               // member chunks of the group
     int32_t out_dst, subtract;
-    int32_t nmc;               // member chunks of the group (blocks per row block)
+    int32_t seg_pstart[SEGMAX + 1];
+    int32_t seg_src[SEGMAX];   // 0 = ws (reduced RHS), 1 = ys (solution)
+    int64_t seg_off[SEGMAX];   // padded position of the segment in a member's work vector
+    int64_t out_off;           // padded position of the output block
+    int64_t sp;                // planar half-stride of the group's work vectors
 };
+constexpr int bcr_wpb(int prec) { return prec ? 8 : 4; }  // waves per block (FP32, FP64): the column split
 
-constexpr int BCR_RB = 8;                            // rows per block of the cyclic-reduction GEMV
-inline int bcr_mc(int prec) { return prec ? 4 : 2; }  // members per block (FP32, FP64)
+// Copy of one apply matrix into the padded layout (setup only).
+struct RepackDesc {
+    const double *src;         // rows x cols, row-major
+    int32_t rows, cols, ld, nseg;
+    int64_t poff;              // destination offset
+    int32_t seg_col[SEGMAX], seg_len[SEGMAX], seg_pstart[SEGMAX];
+};
+void launch_repack(const std::vector<RepackDesc> &d, double *dst64, float *dst32, hipStream_t st);
 
 struct PrecPhase {
     DBuf<BcrTask> tasks[2];    // FP64, FP32 matrices

@@ -4,8 +4,8 @@
 //     (edge/face) DoFs, layered along the last axis: every level eliminates the
 //     odd-positioned blocks (explicit dense inverses) and couples the even ones.
 // Application to the two right-hand sides (real and imaginary halves) is one
-// batched multi-GEMV launch per level and direction; systems whose matrices are
-// identical share one factor and are served by the same matrix rows.
+// batched MFMA launch per level and direction; systems whose matrices are identical
+// share one factor, and their right-hand sides become extra columns of one product.
 #include "kernels.h"
 
 namespace thm {
@@ -397,7 +397,8 @@ void launch_convert(const double *a, float *b, int64_t n, hipStream_t st) {
 }
 
 // ------------------------------------------------------------------ application (batched)
-// ws[t] = r[skel_dof[t]] - sum over cells c of t of (F_c r_int(c))[local t]
+// ws[t] = r[skel_dof[t]] - sum over cells c of t of (F_c r_int(c))[local t], stored
+// planar at the padded position: real parts in ws[0, sp), imaginary parts in ws[sp, 2 sp).
 template <class T>
 __global__ void __launch_bounds__(256) k_cond_fwd(const PrecDesc *__restrict__ pd, const int64_t *__restrict__ off,
                                                   const int64_t *__restrict__ soff, const int32_t *__restrict__ blkoff,
@@ -410,7 +411,7 @@ __global__ void __launch_bounds__(256) k_cond_fwd(const PrecDesc *__restrict__ p
     const int64_t t = (int64_t)(blockIdx.x - blkoff[s]) * 256 + threadIdx.x;
     if (t >= d.n_skel) return;
     const T2 *r = reinterpret_cast<const T2 *>(rb + off[s]);
-    T2 *ws = reinterpret_cast<T2 *>(wsb + soff[s]);
+    T *ws = wsb + soff[s];
     const T *F = reinterpret_cast<const T *>(d.F);
     T2 acc = r[d.skel_dof[t]];
     for (int32_t e = d.cond_ptr[t]; e < d.cond_ptr[t + 1]; ++e) {
@@ -425,120 +426,227 @@ __global__ void __launch_bounds__(256) k_cond_fwd(const PrecDesc *__restrict__ p
             acc.y -= fv * rv.y;
         }
     }
-    ws[t] = acc;
+    const int32_t p = d.skel_pos[t];
+    ws[p] = acc.x;
+    ws[d.sp + p] = acc.y;
 }
 
-// Cyclic-reduction multi-GEMV.  A block owns RB consecutive rows of one task; its
-// four waves split the columns (each wave a contiguous quarter, lanes strided by
-// 64) and the partial sums are combined through LDS.  Members of the task's factor
-// group are processed MC at a time, so every loaded input element serves RB rows
-// and every matrix element MC members.
-//   subtract = 1:  y[row] = y[row] - sum_seg M[row, seg] x_seg   (reduction of RHS)
-//   subtract = 0:  y[row] =          sum_seg M[row, seg] x_seg   (back substitution)
-constexpr int RB = 8;  // rows per block
-template <class T> struct McOf { static constexpr int v = 4; };
-template <> struct McOf<double> { static constexpr int v = 2; };
+// ------------------------------------------------------------------ cyclic-reduction apply (MFMA)
+// Every task is a dense product Y = M X: M is rows x ld (one cyclic-reduction block:
+// an inverse and/or couplings), X holds the task's input segments of every member of
+// the factor group as columns (real and imaginary part of each member are separate
+// columns, so 8 members fill one 16-wide n tile).
+//   subtract = 1:  y[row] = y[row] - (M X)[row]   (reduction of the right-hand side)
+//   subtract = 0:  y[row] =          (M X)[row]   (back substitution / last blocks)
+// A block owns 32 rows (two 16 x 16 MFMA tiles) and up to 16 members; its waves split
+// the columns into contiguous ranges and the partial tiles are summed through LDS in a
+// fixed order, so the result does not depend on scheduling.  Within a 32-column step,
+// lane group g (lanes 16 g .. 16 g + 15) feeds the MFMA k index g with columns
+// k0 + 8 g + j for j = 0..7 (one 16-byte aligned run per lane), row i16 of M and column
+// i16 of X; the sum over k is order-free, so this permutation is exact.
+template <class T> struct Mfma;
+// Both forms take A[i][k] from lane i + 16 k and B[k][j] from lane j + 16 k; they
+// differ in where accumulator v of lane j + 16 g sits: row 4 g + v (f32) or row
+// g + 4 v (f64).
+template <> struct Mfma<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 op(float a, float b, v4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int g, int v) { return 4 * g + v; }
+};
+template <> struct Mfma<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 op(double a, double b, v4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int g, int v) { return g + 4 * v; }
+};
+
+// 8 consecutive values from global memory (16-byte aligned), as 16-byte loads.
 template <class T>
-__global__ void __launch_bounds__(256) k_bcr_gemv(const BcrTask *__restrict__ tasks, const int32_t *__restrict__ blkoff,
-                                                  int ntasks, const int32_t *__restrict__ memb_ptr,
-                                                  const int32_t *__restrict__ memb, const int64_t *__restrict__ soff,
-                                                  const int32_t *__restrict__ mask, T *__restrict__ wsb,
-                                                  T *__restrict__ ysb) {
-    using T2 = typename P2<T>::t;
-    constexpr int MC = McOf<T>::v;  // members per block
-    __shared__ T red[4][RB][MC][2];
-    const int t = find_sys2(blkoff, ntasks, blockIdx.x);
-    const BcrTask &tk = tasks[t];
+__device__ __forceinline__ void load8(const T *p, T (&v)[8]) {
+    typedef T vec16 __attribute__((ext_vector_type(16 / sizeof(T))));
+    typedef const __attribute__((address_space(1))) vec16 gvec16;
+    constexpr int per = 16 / sizeof(T);
+    const gvec16 *q = (const gvec16 *)p;
+#pragma unroll
+    for (int i = 0; i < 8 / per; ++i) {
+        const vec16 x = q[i];
+#pragma unroll
+        for (int j = 0; j < per; ++j) v[i * per + j] = x[j];
+    }
+}
+
+template <class T, int WPB>
+struct BcrShared {
+    T red[WPB][2 * BCR_NM][BCR_RT + 4];  // partial tiles: [wave][n][row]
+    int32_t pstart[SEGMAX + 1];
+    int32_t src[SEGMAX];
+    int64_t delta[SEGMAX];               // segment position in the vector minus its first column
+};
+
+// Operands of one 32-column step: 8 columns of two M rows and of NNT X columns per lane.
+template <class T, int NNT>
+struct BcrStep {
+    T a0[8], a1[8], b[NNT][8];
+};
+
+// Lane-private walk over the input segments.  bseg[nt] + k addresses column k of the
+// lane's X column; columns past the padded width (zero in M) read the last 8 columns
+// of the last segment instead, and lanes of absent members read the chunk's first
+// member (their output columns are never stored), so every load is in bounds and
+// every value that meets a nonzero M entry is the right one.
+template <class T, int WPB, int NNT>
+struct BcrWalk {
+    int sg = 0, nextb = 0;
+    const T *bseg[NNT];
+    __device__ __forceinline__ void enter(const BcrTask &tk, const BcrShared<T, WPB> &sh, const int64_t (&bbase)[NNT],
+                                          int k, const T *wsb, const T *ysb) {
+        while (sg + 1 < tk.nseg && k >= sh.pstart[sg + 1]) ++sg;
+        nextb = sg + 1 < tk.nseg ? sh.pstart[sg + 1] : 0x7fffffff;
+        const T *src = sh.src[sg] ? ysb : wsb;
+#pragma unroll
+        for (int nt = 0; nt < NNT; ++nt) bseg[nt] = src + bbase[nt] + sh.delta[sg];
+    }
+};
+
+template <class T, int WPB, int NNT>
+__device__ __forceinline__ void bcr_fetch(BcrStep<T, NNT> &o, BcrWalk<T, WPB, NNT> &w, const BcrTask &tk,
+                                          const BcrShared<T, WPB> &sh, const int64_t (&bbase)[NNT], const T *A0,
+                                          const T *A1, int k, int kvalid, const T *wsb, const T *ysb) {
+    load8(A0 + k, o.a0);
+    load8(A1 + k, o.a1);
+    if (k >= w.nextb) w.enter(tk, sh, bbase, k, wsb, ysb);
+    const int kk = k < kvalid ? k : kvalid - 8;
+#pragma unroll
+    for (int nt = 0; nt < NNT; ++nt) load8(w.bseg[nt] + kk, o.b[nt]);
+}
+
+template <class T, int NNT>
+__device__ __forceinline__ void bcr_mma(const BcrStep<T, NNT> &o, typename Mfma<T>::v4 (&acc)[2][NNT]) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+#pragma unroll
+        for (int nt = 0; nt < NNT; ++nt) {
+            acc[0][nt] = Mfma<T>::op(o.a0[j], o.b[nt][j], acc[0][nt]);
+            acc[1][nt] = Mfma<T>::op(o.a1[j], o.b[nt][j], acc[1][nt]);
+        }
+}
+
+template <class T, int WPB, int NNT>
+__device__ __forceinline__ void bcr_tile(const BcrTask &tk, BcrShared<T, WPB> &sh, int row0, int mb, int m1,
+                                         const int32_t *__restrict__ memb, const int64_t *__restrict__ soff,
+                                         const int32_t *__restrict__ mask, T *__restrict__ wsb,
+                                         T *__restrict__ ysb) {
+    using V4 = typename Mfma<T>::v4;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int local = blockIdx.x - blkoff[t];
-    const int row0 = (local / tk.nmc) * RB;
-    const int mchunk = local % tk.nmc;
-    const int nr = min(RB, tk.rows - row0);
-    const T *M0 = reinterpret_cast<const T *>(tk.M) + (int64_t)row0 * tk.cols;
-    const int m0 = memb_ptr[tk.group], m1 = memb_ptr[tk.group + 1];
-    // this wave's column quarter [c0, c1) of the concatenated segments
-    const int q4 = (tk.cols + 3) / 4;
-    const int c0 = wave * q4, c1 = min(tk.cols, c0 + q4);
-    {
-        const int mb = m0 + mchunk * MC;
-        int sys[MC];
-        bool on[MC];
+    const int i16 = lane & 15, g = lane >> 4;
+    const T *M = static_cast<const T *>(tk.M);
+    const int64_t ld = tk.ld;
+    // rows past the end load the last row again; their results are dropped
+    const T *A0 = M + min(row0 + i16, tk.rows - 1) * ld;
+    const T *A1 = M + min(row0 + 16 + i16, tk.rows - 1) * ld;
+    int64_t bbase[NNT];
 #pragma unroll
-        for (int q = 0; q < MC; ++q) {
-            sys[q] = mb + q < m1 ? memb[mb + q] : memb[m0];
-            on[q] = mb + q < m1 && (!mask || mask[sys[q]]);
-        }
-        bool any = false;
+    for (int nt = 0; nt < NNT; ++nt) {
+        const int mi = mb + 8 * nt + (i16 >> 1);
+        bbase[nt] = soff[memb[mi < m1 ? mi : mb]] + (i16 & 1) * tk.sp;
+    }
+    V4 acc[2][NNT];
 #pragma unroll
-        for (int q = 0; q < MC; ++q) any = any || on[q];
-        if (!any) return;  // uniform across the block
-        T ar[RB][MC], ai[RB][MC];
+    for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-        for (int r = 0; r < RB; ++r)
-#pragma unroll
-            for (int q = 0; q < MC; ++q) ar[r][q] = ai[r][q] = 0;
-        int sbeg = 0;
-        for (int sg = 0; sg < tk.nseg; ++sg) {
-            const int len = tk.seg_len[sg];
-            const int lo = max(c0, sbeg), hi = min(c1, sbeg + len);
-            if (lo < hi) {
-                const T *src = tk.seg_src[sg] ? ysb : wsb;
-                const T2 *xq[MC];
-#pragma unroll
-                for (int q = 0; q < MC; ++q)
-                    xq[q] = reinterpret_cast<const T2 *>(src + soff[sys[q]]) + tk.seg_off[sg] - sbeg;
-#pragma unroll 2
-                for (int c = lo + lane; c < hi; c += 64) {
-                    T2 xv[MC];
-#pragma unroll
-                    for (int q = 0; q < MC; ++q) xv[q] = on[q] ? xq[q][c] : T2{0, 0};
-                    T a[RB];
-#pragma unroll
-                    for (int r = 0; r < RB; ++r) a[r] = r < nr ? M0[(int64_t)r * tk.cols + c] : (T)0;
-#pragma unroll
-                    for (int r = 0; r < RB; ++r)
-#pragma unroll
-                        for (int q = 0; q < MC; ++q) {
-                            ar[r][q] += a[r] * xv[q].x;
-                            ai[r][q] += a[r] * xv[q].y;
-                        }
-                }
-            }
-            sbeg += len;
-        }
-#pragma unroll
-        for (int r = 0; r < RB; ++r)
-#pragma unroll
-            for (int q = 0; q < MC; ++q) {
-                T re = ar[r][q], im = ai[r][q];
-#pragma unroll
-                for (int o = 32; o > 0; o >>= 1) {
-                    re += __shfl_xor(re, o, 64);
-                    im += __shfl_xor(im, o, 64);
-                }
-                if (lane == 0) {
-                    red[wave][r][q][0] = re;
-                    red[wave][r][q][1] = im;
-                }
-            }
-        __syncthreads();
-        if (threadIdx.x < RB * MC) {
-            const int r = threadIdx.x / MC, q = threadIdx.x % MC;
-            if (r < nr && on[q]) {
-                const T re = red[0][r][q][0] + red[1][r][q][0] + red[2][r][q][0] + red[3][r][q][0];
-                const T im = red[0][r][q][1] + red[1][r][q][1] + red[2][r][q][1] + red[3][r][q][1];
-                T2 *y = reinterpret_cast<T2 *>((tk.out_dst ? ysb : wsb) + soff[sys[q]]) + tk.out_off + row0 + r;
-                if (tk.subtract) {
-                    T2 v = *y;
-                    v.x -= re;
-                    v.y -= im;
-                    *y = v;
-                } else {
-                    *y = T2{re, im};
-                }
-            }
+        for (int nt = 0; nt < NNT; ++nt) acc[mt][nt] = V4{0, 0, 0, 0};
+    const int kbeg = wave * tk.kq;
+    const int kend = min(tk.ld, kbeg + tk.kq);
+    const int kvalid = sh.pstart[tk.nseg];
+    if (kbeg < kend) {
+        // two operand buffers in turn: the loads of the next step are in flight while
+        // the MFMAs of the current one run
+        BcrWalk<T, WPB, NNT> w;
+        w.enter(tk, sh, bbase, kbeg + 8 * g, wsb, ysb);
+        BcrStep<T, NNT> p, q;
+        int k = kbeg + 8 * g;
+        bcr_fetch(p, w, tk, sh, bbase, A0, A1, k, kvalid, wsb, ysb);
+        for (int k0 = kbeg;;) {
+            if (k0 + BCR_KS < kend) bcr_fetch(q, w, tk, sh, bbase, A0, A1, k + BCR_KS, kvalid, wsb, ysb);
+            bcr_mma(p, acc);
+            k0 += BCR_KS;
+            k += BCR_KS;
+            if (k0 >= kend) break;
+            if (k0 + BCR_KS < kend) bcr_fetch(p, w, tk, sh, bbase, A0, A1, k + BCR_KS, kvalid, wsb, ysb);
+            bcr_mma(q, acc);
+            k0 += BCR_KS;
+            k += BCR_KS;
+            if (k0 >= kend) break;
         }
     }
+    // accumulator v: row Mfma::row(g, v) of m tile mt, column i16 of n tile nt
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NNT; ++nt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                sh.red[wave][16 * nt + i16][16 * mt + Mfma<T>::row(g, v)] = acc[mt][nt][v];
+    __syncthreads();
+    constexpr int NOUT = BCR_RT * 16 * NNT;
+    for (int o = threadIdx.x; o < NOUT; o += 64 * WPB) {
+        const int n = o / BCR_RT, r = o % BCR_RT;
+        const int mi = mb + (n >> 1);
+        if (row0 + r >= tk.rows || mi >= m1) continue;
+        const int s = memb[mi];
+        if (mask && !mask[s]) continue;
+        T v = 0;
+#pragma unroll
+        for (int w = 0; w < WPB; ++w) v += sh.red[w][n][r];
+        T *y = (tk.out_dst ? ysb : wsb) + soff[s] + (n & 1) * tk.sp + tk.out_off + row0 + r;
+        if (tk.subtract)
+            *y -= v;
+        else
+            *y = v;
+    }
+}
+
+template <class T, int WPB>
+__global__ void __launch_bounds__(64 * WPB) k_bcr_mfma(const BcrTask *__restrict__ tasks,
+                                                       const int32_t *__restrict__ blkoff, int ntasks,
+                                                       const int32_t *__restrict__ memb_ptr,
+                                                       const int32_t *__restrict__ memb,
+                                                       const int64_t *__restrict__ soff,
+                                                       const int32_t *__restrict__ mask, T *__restrict__ wsb,
+                                                       T *__restrict__ ysb) {
+    __shared__ BcrShared<T, WPB> sh;
+    // Workgroups are dealt to the 8 XCDs round-robin; renumber them so that the row
+    // tiles of one task (which read the same input vectors) run on the same XCD and
+    // share its L2.
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int q = nb >> 3, rem = nb & 7, x = b & 7, i = b >> 3;
+    const int lb = x < rem ? x * (q + 1) + i : rem * (q + 1) + (x - rem) * q + i;
+    const int t = find_sys2(blkoff, ntasks, lb);
+    const BcrTask &tk = tasks[t];
+    const int local = lb - blkoff[t];
+    const int rt = local / tk.nmc, mchunk = local - rt * tk.nmc;
+    const int m1 = memb_ptr[tk.group + 1];
+    const int mb = memb_ptr[tk.group] + mchunk * 8 * tk.nnt;
+    bool any = false;
+    for (int j = 0; j < 8 * tk.nnt; ++j)
+        if (mb + j < m1 && (!mask || mask[memb[mb + j]])) any = true;
+    if (!any) return;  // same decision in every thread of the block
+    if (threadIdx.x <= SEGMAX) {
+        const int j = threadIdx.x;
+        sh.pstart[j] = j <= tk.nseg ? tk.seg_pstart[j] : tk.seg_pstart[tk.nseg];
+        if (j < SEGMAX) {
+            sh.src[j] = tk.seg_src[j];
+            sh.delta[j] = j < tk.nseg ? tk.seg_off[j] - tk.seg_pstart[j] : 0;
+        }
+    }
+    __syncthreads();
+    if (tk.nnt == 1)
+        bcr_tile<T, WPB, 1>(tk, sh, rt * BCR_RT, mb, m1, memb, soff, mask, wsb, ysb);
+    else
+        bcr_tile<T, WPB, 2>(tk, sh, rt * BCR_RT, mb, m1, memb, soff, mask, wsb, ysb);
 }
 
 // x[g] = ys[pos(g)] on skeleton DoFs; interiors: x_i = Kii^{-1} r_i - F^T x_e.
@@ -553,10 +661,11 @@ __global__ void __launch_bounds__(256) k_cond_bwd(const PrecDesc *__restrict__ p
     const PrecDesc d = pd[s];
     const int64_t g = (int64_t)(blockIdx.x - blkoff[s]) * 256 + threadIdx.x;
     if (g >= d.n) return;
-    const T2 *ys = reinterpret_cast<const T2 *>(ysb + soff[s]);
+    const T *ys = ysb + soff[s];
     T2 *x = reinterpret_cast<T2 *>(xb + off[s]);
     if (g < d.cell_off) {
-        x[g] = ys[d.dof_pos[g]];
+        const int32_t p = d.dof_pos[g];
+        x[g] = T2{ys[p], ys[d.sp + p]};
         return;
     }
     const T2 *r = reinterpret_cast<const T2 *>(rb + off[s]);
@@ -574,25 +683,59 @@ __global__ void __launch_bounds__(256) k_cond_bwd(const PrecDesc *__restrict__ p
     const int32_t *cd = d.cell_dofs + c * d.n_loc;
     for (int le = 0; le < d.ne; ++le) {
         const T f = F[le * d.n_int + m];
-        const T2 xe = ys[d.dof_pos[cd[le]]];
-        acc.x -= f * xe.x;
-        acc.y -= f * xe.y;
+        const int32_t p = d.dof_pos[cd[le]];
+        acc.x -= f * ys[p];
+        acc.y -= f * ys[d.sp + p];
     }
     x[g] = acc;
 }
 
 template <class T>
 void launch_bcr_phases(const PrecBatch &P, const int32_t *mask, T *ws, T *ys, hipStream_t st) {
-    const int prec = sizeof(T) == 8 ? 0 : 1;
+    constexpr int prec = sizeof(T) == 8 ? 0 : 1;
+    constexpr int wpb = bcr_wpb(prec);
     for (const PrecPhase &ph : P.phases)
         if (ph.sched[prec].nblocks)
-            k_bcr_gemv<T><<<ph.sched[prec].nblocks, 256, 0, st>>>(ph.tasks[prec].p, ph.sched[prec].blkoff.p,
-                                                                   ph.ntasks, P.memb_ptr.p, P.memb.p, P.soff.p, mask,
-                                                                   ws, ys);
+            k_bcr_mfma<T, wpb><<<ph.sched[prec].nblocks, 64 * wpb, 0, st>>>(
+                ph.tasks[prec].p, ph.sched[prec].blkoff.p, ph.ntasks, P.memb_ptr.p, P.memb.p, P.soff.p, mask, ws, ys);
     THM_HIP(hipGetLastError());
 }
 template void launch_bcr_phases<double>(const PrecBatch &, const int32_t *, double *, double *, hipStream_t);
 template void launch_bcr_phases<float>(const PrecBatch &, const int32_t *, float *, float *, hipStream_t);
+
+// ------------------------------------------------------------------ padded copies (setup)
+__global__ void __launch_bounds__(256) k_repack(const RepackDesc *__restrict__ ds, const int32_t *__restrict__ blkoff,
+                                                int nd, double *__restrict__ dst64, float *__restrict__ dst32) {
+    const int di = find_sys2(blkoff, nd, blockIdx.x);
+    const RepackDesc &d = ds[di];
+    const int64_t e = (int64_t)(blockIdx.x - blkoff[di]) * 256 + threadIdx.x;
+    if (e >= (int64_t)d.rows * d.ld) return;
+    const int64_t r = e / d.ld;
+    const int pc = (int)(e - r * d.ld);
+    double v = 0.0;
+    for (int q = 0; q < d.nseg; ++q) {
+        const int j = pc - d.seg_pstart[q];
+        if (j >= 0 && j < d.seg_len[q]) {
+            v = d.src[r * d.cols + d.seg_col[q] + j];
+            break;
+        }
+    }
+    dst64[d.poff + e] = v;
+    dst32[d.poff + e] = (float)v;
+}
+
+void launch_repack(const std::vector<RepackDesc> &d, double *dst64, float *dst32, hipStream_t st) {
+    if (d.empty()) return;
+    std::vector<int64_t> units(d.size());
+    for (size_t i = 0; i < d.size(); ++i) units[i] = (int64_t)d[i].rows * d[i].ld;
+    Sched sc;
+    sc.build(units, 256, st);
+    DBuf<RepackDesc> dd;
+    dd.upload(d, st);
+    if (sc.nblocks) k_repack<<<sc.nblocks, 256, 0, st>>>(dd.p, sc.blkoff.p, (int)d.size(), dst64, dst32);
+    THM_HIP(hipGetLastError());
+    THM_HIP(hipStreamSynchronize(st));
+}
 
 template <class T>
 void launch_prec_apply(const PrecBatch &P, const PrecDesc *d, const int64_t *off, int ns, const int32_t *mask,

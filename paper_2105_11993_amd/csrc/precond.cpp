@@ -149,6 +149,27 @@ static void plan(Factor &f) {
     }
     off += (int64_t)f.top_n * f.top_n;
     f.mat_elems = off;
+    // padded copies for the apply: each input segment starts at its layer's aligned
+    // width, rows are padded to a multiple of the MFMA column step
+    int64_t poff = 0;
+    auto pad = [&](Factor::Blk &b) {
+        int c = 0;
+        for (int q = 0; q < b.nseg; ++q) {
+            b.seg_pstart[q] = c;
+            const int k = b.seg_layer[q];
+            c += (int)(f.pboff[k + 1] - f.pboff[k]);
+        }
+        b.seg_pstart[b.nseg] = c;
+        b.ld = (c + BCR_KS - 1) / BCR_KS * BCR_KS;
+        b.poff = poff;
+        poff += (int64_t)b.rows * b.ld;
+    };
+    for (auto &lev : f.fwd)
+        for (auto &b : lev) pad(b);
+    for (auto &lev : f.bwd)
+        for (auto &b : lev) pad(b);
+    for (auto &b : f.tops) pad(b);
+    f.matp_elems = poff;
 }
 
 void setup_precond(const std::vector<thm_system *> &all, hipStream_t st, bool share) {
@@ -186,6 +207,8 @@ void setup_precond(const std::vector<thm_system *> &all, hipStream_t st, bool sh
         f.nlayers = L.nlayers;
         f.bsize = L.bsize;
         f.boff = L.boff;
+        f.pboff = L.pboff;
+        f.sp = L.n_skel_pad;
         f.n_int = t.n_int;
         f.ne = t.n_loc - t.n_int;
         f.n_cells = t.n_cells;
@@ -372,8 +395,34 @@ void setup_precond(const std::vector<thm_system *> &all, hipStream_t st, bool sh
     }
     for (Work &w : W) {
         Factor &f = *w.f;
-        f.mat32.alloc(f.mat.n);
-        launch_convert(f.mat.p, f.mat32.p, f.mat.n, st);
+        std::vector<RepackDesc> rd;
+        auto add = [&](const Factor::Blk &b) {
+            RepackDesc d{};
+            d.src = f.mat.p + b.off;
+            d.rows = b.rows;
+            d.cols = b.cols;
+            d.ld = b.ld;
+            d.nseg = b.nseg;
+            d.poff = b.poff;
+            int c = 0;
+            for (int q = 0; q < b.nseg; ++q) {
+                d.seg_col[q] = c;
+                d.seg_len[q] = f.bsize[b.seg_layer[q]];
+                d.seg_pstart[q] = b.seg_pstart[q];
+                c += d.seg_len[q];
+            }
+            rd.push_back(d);
+        };
+        for (auto &lev : f.fwd)
+            for (auto &b : lev) add(b);
+        for (auto &lev : f.bwd)
+            for (auto &b : lev) add(b);
+        for (auto &b : f.tops) add(b);
+        f.matp.alloc(std::max<int64_t>(f.matp_elems, 1));
+        f.matp32.alloc(std::max<int64_t>(f.matp_elems, 1));
+        launch_repack(rd, f.matp.p, f.matp32.p, st);
+        THM_HIP(hipStreamSynchronize(st));
+        f.mat.release();
         f.kiinv32.alloc(f.kiinv.n);
         f.F32.alloc(f.F.n);
         launch_convert(f.kiinv.p, f.kiinv32.p, f.kiinv.n, st);
@@ -392,7 +441,7 @@ void setup_precond(const std::vector<thm_system *> &all, hipStream_t st, bool sh
     const double dt = now_ms() - t0;
     for (auto &f : facs) {
         f->setup_ms = dt;
-        f->bytes = 8 * (f->mat_elems + (int64_t)f->kiinv.n + (int64_t)f->F.n);
+        f->bytes = 12 * (f->matp_elems + (int64_t)f->kiinv.n + (int64_t)f->F.n);
     }
 }
 

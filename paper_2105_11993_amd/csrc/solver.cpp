@@ -251,8 +251,10 @@ void Ctx::build(const std::vector<thm_system *> &s, int m, hipStream_t stream) {
         d.n_int = t.n_int;
         d.ne = t.n_loc - t.n_int;
         d.nlayers = S.L.nlayers;
+        d.sp = S.L.n_skel_pad;
         d.cell_dofs = S.cell_dofs.p;
         d.skel_dof = S.Lskel_dof.p;
+        d.skel_pos = S.Lskel_pos.p;
         d.dof_pos = S.Ldof_pos.p;
         d.cond_ptr = S.Lcond_ptr.p;
         d.cond_cell = S.Lcond_cell.p;
@@ -264,7 +266,7 @@ void Ctx::build(const std::vector<thm_system *> &s, int m, hipStream_t stream) {
         p32[i].kiinv = f.kiinv32.p;
         p32[i].F = f.F32.p;
         soff[i] = so;
-        so += 2 * nsk[i];
+        so += 2 * S.L.n_skel_pad;  // planar: real block, then imaginary block
         so = (so + 63) & ~int64_t(63);
     }
     mat64.upload(h64, st);
@@ -290,50 +292,52 @@ void Ctx::build(const std::vector<thm_system *> &s, int m, hipStream_t stream) {
     int nlev = 0;
     for (Factor *f : groups) nlev = std::max(nlev, (int)f->fwd.size());
     auto task = [&](const Factor &f, const Factor::Blk &b, int g, int prec) {
-        (void)0;
         BcrTask t{};
-        t.M = prec ? (const void *)(f.mat32.p + b.off) : (const void *)(f.mat.p + b.off);
+        t.M = prec ? (const void *)(f.matp32.p + b.poff) : (const void *)(f.matp.p + b.poff);
         t.rows = b.rows;
-        t.cols = b.cols;
+        t.ld = b.ld;
         t.nseg = b.nseg;
         t.group = g;
+        const int wpb = bcr_wpb(prec);
+        t.kq = ((b.ld + wpb - 1) / wpb + BCR_KS - 1) / BCR_KS * BCR_KS;
+        const int nm = (int)members[g].size();
+        t.nnt = nm > 8 ? 2 : 1;
+        t.nmc = (nm + 8 * t.nnt - 1) / (8 * t.nnt);
+        for (int q = 0; q <= SEGMAX; ++q) t.seg_pstart[q] = q <= b.nseg ? b.seg_pstart[q] : b.seg_pstart[b.nseg];
         for (int q = 0; q < SEGMAX; ++q) {
-            t.seg_len[q] = q < b.nseg ? f.bsize[b.seg_layer[q]] : 0;
             t.seg_src[q] = q < b.nseg ? b.seg_src[q] : 0;
-            t.seg_off[q] = q < b.nseg ? f.boff[b.seg_layer[q]] : 0;
+            t.seg_off[q] = q < b.nseg ? f.pboff[b.seg_layer[q]] : 0;
         }
-        t.out_off = f.boff[b.layer];
+        t.out_off = f.pboff[b.layer];
         t.out_dst = b.out_dst;
         t.subtract = b.subtract;
-        const int nm = (int)members[g].size(), mc = bcr_mc(prec);
-        t.nmc = (nm + mc - 1) / mc;
+        t.sp = f.sp;
         return t;
     };
     P.phases.clear();
     bcr_bytes[0].clear();
     bcr_bytes[1].clear();
+    // Algorithmic bytes of a phase: every matrix element once (true, unpadded size), the
+    // input segments of each member once, the output block written (and read when the
+    // task subtracts).
     auto add_phase = [&](auto pick) {
         std::vector<BcrTask> t64, t32;
         std::vector<int64_t> u64, u32;
+        double elems = 0.0, vec = 0.0;
         for (size_t g = 0; g < groups.size(); ++g)
             for (const Factor::Blk *b : pick(*groups[g])) {
                 t64.push_back(task(*groups[g], *b, (int)g, 0));
                 t32.push_back(task(*groups[g], *b, (int)g, 1));
-                const int64_t rb = (b->rows + BCR_RB - 1) / BCR_RB;
+                const int64_t rb = (b->rows + BCR_RT - 1) / BCR_RT;
                 u64.push_back(rb * t64.back().nmc);
                 u32.push_back(rb * t32.back().nmc);
+                const double nm = (double)members[g].size();
+                elems += (double)b->rows * b->cols;
+                vec += nm * 2.0 * (b->cols + b->rows * (b->subtract ? 2.0 : 1.0));
             }
         if (t64.empty()) return;
-        for (int prec = 0; prec < 2; ++prec) {
-            const double v = prec ? 4.0 : 8.0;
-            double by = 0.0;
-            const auto &tt = prec ? t32 : t64;
-            for (const BcrTask &t : tt) {
-                const double nm = (double)members[t.group].size();
-                by += (double)t.rows * t.cols * v + nm * 2.0 * v * (t.cols + t.rows * (t.subtract ? 2.0 : 1.0));
-            }
-            bcr_bytes[prec].push_back(by);
-        }
+        bcr_bytes[0].push_back(8.0 * (elems + vec));
+        bcr_bytes[1].push_back(4.0 * (elems + vec));
         P.phases.emplace_back();
         PrecPhase &ph = P.phases.back();
         ph.ntasks = (int)t64.size();

@@ -18,13 +18,21 @@ struct Factor {
     std::vector<int64_t> boff;
     int n_int = 0, ne = 0;
     int64_t n_cells = 0;
-    DBuf<double> kiinv, F, mat;
-    DBuf<float> kiinv32, F32, mat32;
+    std::vector<int64_t> pboff;  // padded layer offsets of the skeleton work vectors
+    int64_t sp = 0;              // padded skeleton length (one planar half)
+    DBuf<double> kiinv, F;
+    DBuf<float> kiinv32, F32;
+    DBuf<double> mat;            // apply matrices during setup (rows x cols, segments packed)
+    DBuf<double> matp;           // apply matrices, padded (rows x ld, segments aligned)
+    DBuf<float> matp32;
     struct Blk {
         int layer;
-        int64_t off;
+        int64_t off;             // in mat
+        int64_t poff;            // in matp / matp32
         int rows, cols, nseg;
+        int ld;                  // padded row length (multiple of BCR_KS)
         int seg_layer[SEGMAX], seg_src[SEGMAX];
+        int seg_pstart[SEGMAX + 1];  // padded column of each segment; [nseg] = padded width
         int out_dst, subtract;
     };
     std::vector<std::vector<Blk>> fwd, bwd;   // per level
@@ -36,7 +44,7 @@ struct Factor {
     std::vector<int> top_pos;
     int64_t top_off = 0;
     int top_n = 0;
-    int64_t mat_elems = 0, bytes = 0;
+    int64_t mat_elems = 0, matp_elems = 0, bytes = 0;
     double setup_ms = 0.0;
 };
 }
@@ -68,7 +76,7 @@ struct thm_system {
     thm::DBuf<int32_t> d2c_ptr, d2c_src;
 
     // preconditioner: skeleton maps of this system and the (possibly shared) factor
-    thm::DBuf<int32_t> Lskel_dof, Ldof_pos, Lcond_ptr, Lcond_cell, Lcond_loc;
+    thm::DBuf<int32_t> Lskel_dof, Lskel_pos, Ldof_pos, Lcond_ptr, Lcond_cell, Lcond_loc;
     std::shared_ptr<thm::Factor> fac;
 
     // domain decomposition

@@ -284,7 +284,14 @@ static void assemble_system(thm_system &S, const thm_problem &p, uint32_t iface_
     build_side_csr(t, S.sides_inc, S.Minc);
     build_layering(t, S.dir, S.L);
     S.Lskel_dof.upload(S.L.skel_dof, st);
-    S.Ldof_pos.upload(S.L.dof_pos, st);
+    S.Lskel_pos.upload(S.L.skel_pos, st);
+    {
+        // global DoF -> padded position in the skeleton work vectors (-1: interior)
+        std::vector<int32_t> vpos(S.L.dof_pos.size(), -1);
+        for (size_t g = 0; g < vpos.size(); ++g)
+            if (S.L.dof_pos[g] >= 0) vpos[g] = S.L.skel_pos[S.L.dof_pos[g]];
+        S.Ldof_pos.upload(vpos, st);
+    }
     S.Lcond_ptr.upload(S.L.cond_ptr, st);
     S.Lcond_cell.upload(S.L.cond_cell, st);
     S.Lcond_loc.upload(S.L.cond_loc, st);

@@ -97,6 +97,8 @@ struct Side {
 };
 
 // Block-tridiagonal layering of the skeleton (non-interior) DoFs.
+constexpr int SKEL_ALIGN = 8;
+
 struct Layering {
     int nlayers = 0;
     std::vector<int32_t> bsize;          // per layer
@@ -106,6 +108,11 @@ struct Layering {
     int64_t n_skel = 0, sinv_total = 0, lf_total = 0;
     std::vector<int32_t> skel_dof;       // skeleton position -> global DoF
     std::vector<int32_t> dof_pos;        // global DoF -> skeleton position (-1: interior)
+    // Layout of the preconditioner's skeleton work vectors: every layer starts at a
+    // multiple of SKEL_ALIGN entries (the tail of a layer is zero padding).
+    std::vector<int64_t> pboff;          // padded offset of layer k (nlayers + 1 entries)
+    int64_t n_skel_pad = 0;
+    std::vector<int32_t> skel_pos;       // skeleton position -> padded position
     // condensed element entry (cell, u, v over skeleton local DoFs) -> dense target
     std::vector<int64_t> tgt_index;      // unique targets: layer-block linear index (see encode)
     std::vector<int32_t> tgt_ptr;        // per unique target, into tgt_src

@@ -304,6 +304,13 @@ void build_layering(const Topo &t, const std::vector<uint8_t> &dir, Layering &L)
     L.boff.assign(nL + 1, 0);
     for (int k = 0; k < nL; ++k) L.boff[k + 1] = L.boff[k] + L.bsize[k];
     L.n_skel = L.boff[nL];
+    L.pboff.assign(nL + 1, 0);
+    for (int k = 0; k < nL; ++k)
+        L.pboff[k + 1] = L.pboff[k] + (L.bsize[k] + SKEL_ALIGN - 1) / SKEL_ALIGN * SKEL_ALIGN;
+    L.n_skel_pad = L.pboff[nL];
+    L.skel_pos.assign(L.n_skel, 0);
+    for (int k = 0; k < nL; ++k)
+        for (int32_t j = 0; j < L.bsize[k]; ++j) L.skel_pos[L.boff[k] + j] = (int32_t)(L.pboff[k] + j);
     L.skel_dof.assign(L.n_skel, 0);
     L.dof_pos.assign(N, -1);
     {
