@@ -124,6 +124,7 @@ struct PrecDesc {
     const int32_t *skel_dof;   // skeleton position -> global DoF
     const int32_t *skel_pos;   // skeleton position -> padded position in the work vectors
     const int32_t *dof_pos;    // global DoF -> padded position (-1: interior)
+    const int32_t *cell_pos;   // n_cells * ne: padded positions of each cell's skeleton DoFs
     const int32_t *cond_ptr, *cond_cell, *cond_loc;
     const void *kiinv, *F;         // double or float
 };
@@ -149,7 +150,7 @@ struct BcrTask {
     int64_t out_off;           // padded position of the output block
     int64_t sp;                // planar half-stride of the group's work vectors
 };
-constexpr int bcr_wpb(int prec) { return prec ? 8 : 4; }  // waves per block (FP32, FP64): the column split
+constexpr int bcr_wpb(int prec) { return prec ? 4 : 4; }  // waves per block (FP32, FP64): the column split
 
 // Copy of one apply matrix into the padded layout (setup only).
 struct RepackDesc {
@@ -173,15 +174,20 @@ struct PrecBatch {
     int64_t Stot = 0;              // scalars per skeleton slot
     Sched skel;                    // 256 skeleton entries per block
     Sched dofs;                    // 256 DoFs per block
+    Sched cfr;                     // 256 (cell, skeleton local DoF) pairs per block
+    DBuf<int64_t> toff;            // complex offset of each system's per-cell condensation terms
+    int64_t Ttot = 0;              // complex entries of all condensation terms
     DBuf<int32_t> memb_ptr, memb;  // factor group -> member systems
     std::vector<PrecPhase> phases; // forward levels, top, backward levels
 };
 
 template <class T>
 void launch_bcr_phases(const PrecBatch &P, const int32_t *mask, T *ws, T *ys, hipStream_t st);
+// x = diag(K, K)^{-1} r for every system of the batch; ws, ys: skeleton work vectors
+// (PrecBatch::Stot scalars), tw: condensation terms (2 PrecBatch::Ttot scalars).
 template <class T>
 void launch_prec_apply(const PrecBatch &P, const PrecDesc *d, const int64_t *off, int ns, const int32_t *mask,
-                       const T *r, T *x, T *ws, T *ys, hipStream_t st);
+                       const T *r, T *x, T *ws, T *ys, T *tw, hipStream_t st);
 
 // Setup (FP64): condensation, dense block assembly, block LU with explicit inverses.
 void launch_condense(int ncells, int n_loc, int n_int, const double *Kel, const int32_t *cell_dofs,

@@ -140,6 +140,11 @@ template void launch_spmv<float>(int, const MatDesc *, const int64_t *, const Sc
 // least-squares solve are FP64 (complex storage in both modes).
 // Each block owns VCHUNK scalars of one system and writes one partial per wave.
 constexpr int PPT = VCHUNK / 512;  // complex pairs per thread
+constexpr int CG = 4;              // basis columns loaded together
+
+// Loads stay unconditional (so the compiler keeps them all in flight): lanes past the
+// end of a vector read its last element and their contribution is dropped.
+__device__ __forceinline__ int64_t clampi(int64_t i, int64_t np) { return i < np ? i : np - 1; }
 
 template <class T>
 __device__ __forceinline__ void wave_store(double v, double *dst) {
@@ -166,22 +171,30 @@ __global__ void __launch_bounds__(256) k_dots(const int64_t *__restrict__ off, c
 #pragma unroll
     for (int t = 0; t < PPT; ++t) {
         const int64_t i = p0 + t * 256 + threadIdx.x;
-        wv[t] = i < np ? wp[i] : T2{0, 0};
+        const T2 x = wp[clampi(i, np)];
+        wv[t] = i < np ? x : T2{0, 0};  // zero weight past the end
     }
-    for (int c = 0; c <= j; ++c) {
-        const T2 *vc = reinterpret_cast<const T2 *>(V + (int64_t)c * ld + base);
-        double ar = 0.0, ai = 0.0;
+    // columns in groups of CG: all loads of a group are in flight together
+    for (int c0 = 0; c0 <= j; c0 += CG) {
+        T2 v[CG][PPT];
 #pragma unroll
-        for (int t = 0; t < PPT; ++t) {
-            const int64_t i = p0 + t * 256 + threadIdx.x;
-            if (i < np) {
-                const T2 v = vc[i];
-                ar += (double)v.x * (double)wv[t].x + (double)v.y * (double)wv[t].y;
-                ai += (double)v.x * (double)wv[t].y - (double)v.y * (double)wv[t].x;
-            }
+        for (int u = 0; u < CG; ++u) {
+            const T2 *vc = reinterpret_cast<const T2 *>(V + (int64_t)min(c0 + u, j) * ld + base);
+#pragma unroll
+            for (int t = 0; t < PPT; ++t) v[u][t] = vc[clampi(p0 + t * 256 + threadIdx.x, np)];
         }
-        wave_store<T>(ar, pp + 2 * c);
-        wave_store<T>(cplx ? ai : 0.0, pp + 2 * c + 1);
+#pragma unroll
+        for (int u = 0; u < CG; ++u) {
+            if (c0 + u > j) break;
+            double ar = 0.0, ai = 0.0;
+#pragma unroll
+            for (int t = 0; t < PPT; ++t) {
+                ar += (double)v[u][t].x * (double)wv[t].x + (double)v[u][t].y * (double)wv[t].y;
+                ai += (double)v[u][t].x * (double)wv[t].y - (double)v[u][t].y * (double)wv[t].x;
+            }
+            wave_store<T>(ar, pp + 2 * (c0 + u));
+            wave_store<T>(cplx ? ai : 0.0, pp + 2 * (c0 + u) + 1);
+        }
     }
 }
 
@@ -227,21 +240,27 @@ __global__ void __launch_bounds__(256) k_cgs_update(const int64_t *__restrict__ 
 #pragma unroll
     for (int t = 0; t < PPT; ++t) {
         const int64_t i = p0 + t * 256 + threadIdx.x;
-        const T2 v = i < np ? wp[i] : T2{0, 0};
+        const T2 v = wp[clampi(i, np)];
         xr[t] = v.x;
         xi[t] = v.y;
     }
     const double *hs = h + (int64_t)s * ldh;
-    for (int c = 0; c <= j; ++c) {
-        const double hr = hs[2 * c], hi = hs[2 * c + 1];
-        const T2 *vc = reinterpret_cast<const T2 *>(V + (int64_t)c * ld + base);
+    for (int c0 = 0; c0 <= j; c0 += CG) {
+        T2 v[CG][PPT];
 #pragma unroll
-        for (int t = 0; t < PPT; ++t) {
-            const int64_t i = p0 + t * 256 + threadIdx.x;
-            if (i < np) {
-                const T2 v = vc[i];
-                xr[t] -= hr * (double)v.x - hi * (double)v.y;
-                xi[t] -= hr * (double)v.y + hi * (double)v.x;
+        for (int u = 0; u < CG; ++u) {
+            const T2 *vc = reinterpret_cast<const T2 *>(V + (int64_t)min(c0 + u, j) * ld + base);
+#pragma unroll
+            for (int t = 0; t < PPT; ++t) v[u][t] = vc[clampi(p0 + t * 256 + threadIdx.x, np)];
+        }
+#pragma unroll
+        for (int u = 0; u < CG; ++u) {
+            if (c0 + u > j) break;
+            const double hr = hs[2 * (c0 + u)], hi = hs[2 * (c0 + u) + 1];
+#pragma unroll
+            for (int t = 0; t < PPT; ++t) {
+                xr[t] -= hr * (double)v[u][t].x - hi * (double)v[u][t].y;
+                xi[t] -= hr * (double)v[u][t].y + hi * (double)v[u][t].x;
             }
         }
     }
@@ -272,7 +291,8 @@ __global__ void __launch_bounds__(256) k_norm2(const int64_t *__restrict__ off, 
 #pragma unroll
     for (int t = 0; t < VCHUNK / 256; ++t) {
         const int64_t i = i0 + t * 256 + threadIdx.x;
-        if (i < n) { const double v = (double)x[base + i]; a += v * v; }
+        const double v = (double)x[base + clampi(i, n)];
+        a += i < n ? v * v : 0.0;
     }
     wave_store<T>(a, part + ((int64_t)blockIdx.x * NPW + (threadIdx.x >> 6)) * maxcols);
 }
@@ -294,8 +314,8 @@ __global__ void __launch_bounds__(256) k_scale(const int64_t *__restrict__ off, 
 #pragma unroll
     for (int t = 0; t < VCHUNK / 256; ++t) {
         const int64_t i = i0 + t * 256 + threadIdx.x;
+        const TO v = (TO)(a * (double)x[base + clampi(i, n)]);
         if (i < n) {
-            const TO v = (TO)(a * (double)x[base + i]);
             d1[i] = v;
             if (y2) y2[base + i] = v;
         }
@@ -318,16 +338,22 @@ __global__ void __launch_bounds__(256) k_lincomb(const int64_t *__restrict__ off
     double xr[PPT], xi[PPT];
 #pragma unroll
     for (int t = 0; t < PPT; ++t) xr[t] = xi[t] = 0.0;
-    for (int c = 0; c < k; ++c) {
-        const double ar = coef[(int64_t)s * ldc + 2 * c], ai = coef[(int64_t)s * ldc + 2 * c + 1];
-        const T2 *vc = reinterpret_cast<const T2 *>(V + (int64_t)c * ld + base);
+    for (int c0 = 0; c0 < k; c0 += CG) {
+        T2 v[CG][PPT];
 #pragma unroll
-        for (int t = 0; t < PPT; ++t) {
-            const int64_t i = p0 + t * 256 + threadIdx.x;
-            if (i < np) {
-                const T2 v = vc[i];
-                xr[t] += ar * (double)v.x - ai * (double)v.y;
-                xi[t] += ar * (double)v.y + ai * (double)v.x;
+        for (int u = 0; u < CG; ++u) {
+            const T2 *vc = reinterpret_cast<const T2 *>(V + (int64_t)min(c0 + u, k - 1) * ld + base);
+#pragma unroll
+            for (int t = 0; t < PPT; ++t) v[u][t] = vc[clampi(p0 + t * 256 + threadIdx.x, np)];
+        }
+#pragma unroll
+        for (int u = 0; u < CG; ++u) {
+            if (c0 + u >= k) break;
+            const double ar = coef[(int64_t)s * ldc + 2 * (c0 + u)], ai = coef[(int64_t)s * ldc + 2 * (c0 + u) + 1];
+#pragma unroll
+            for (int t = 0; t < PPT; ++t) {
+                xr[t] += ar * (double)v[u][t].x - ai * (double)v[u][t].y;
+                xi[t] += ar * (double)v[u][t].y + ai * (double)v[u][t].x;
             }
         }
     }
@@ -353,7 +379,9 @@ __global__ void __launch_bounds__(256) k_axpy(const int64_t *__restrict__ off, c
 #pragma unroll
     for (int t = 0; t < VCHUNK / 256; ++t) {
         const int64_t i = i0 + t * 256 + threadIdx.x;
-        if (i < n) x[base + i] = (TX)((double)x[base + i] + a * (double)z[base + i]);
+        const int64_t ic = base + clampi(i, n);
+        const TX v = (TX)((double)x[ic] + a * (double)z[ic]);
+        if (i < n) x[base + i] = v;
     }
 }
 

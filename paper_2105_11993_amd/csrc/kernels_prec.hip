@@ -397,35 +397,57 @@ void launch_convert(const double *a, float *b, int64_t n, hipStream_t st) {
 }
 
 // ------------------------------------------------------------------ application (batched)
-// ws[t] = r[skel_dof[t]] - sum over cells c of t of (F_c r_int(c))[local t], stored
-// planar at the padded position: real parts in ws[0, sp), imaginary parts in ws[sp, 2 sp).
+// Condensation terms: tw[c ne + le] = (F_c r_int(c))[le], one thread per cell and
+// skeleton local DoF (the 12-24 interior values of a cell are read by its ne threads).
 template <class T>
-__global__ void __launch_bounds__(256) k_cond_fwd(const PrecDesc *__restrict__ pd, const int64_t *__restrict__ off,
-                                                  const int64_t *__restrict__ soff, const int32_t *__restrict__ blkoff,
-                                                  int ns, const int32_t *__restrict__ mask, const T *__restrict__ rb,
-                                                  T *__restrict__ wsb) {
+__global__ void __launch_bounds__(256) k_cond_fr(const PrecDesc *__restrict__ pd, const int64_t *__restrict__ off,
+                                                 const int64_t *__restrict__ toff, const int32_t *__restrict__ blkoff,
+                                                 int ns, const int32_t *__restrict__ mask, const T *__restrict__ rb,
+                                                 T *__restrict__ twb) {
     using T2 = typename P2<T>::t;
     const int s = find_sys2(blkoff, ns, blockIdx.x);
     if (mask && !mask[s]) return;
-    const PrecDesc d = pd[s];
+    const PrecDesc &d = pd[s];
+    const int64_t e = (int64_t)(blockIdx.x - blkoff[s]) * 256 + threadIdx.x;
+    if (e >= (int64_t)d.n_cells * d.ne) return;
+    const int64_t c = e / d.ne;
+    const T *f = reinterpret_cast<const T *>(d.F) + e * d.n_int;
+    const T2 *ri = reinterpret_cast<const T2 *>(rb + off[s]) + d.cell_off + c * d.n_int;
+    T2 acc{0, 0};
+#pragma unroll 4
+    for (int m = 0; m < d.n_int; ++m) {
+        const T fv = f[m];
+        const T2 rv = ri[m];
+        acc.x += fv * rv.x;
+        acc.y += fv * rv.y;
+    }
+    reinterpret_cast<T2 *>(twb)[toff[s] + e] = acc;
+}
+
+// ws[t] = r[skel_dof[t]] - sum over the cells c of t of (F_c r_int(c))[local t], stored
+// planar at the padded position: real parts in ws[0, sp), imaginary parts in ws[sp, 2 sp).
+template <class T>
+__global__ void __launch_bounds__(256) k_cond_fwd(const PrecDesc *__restrict__ pd, const int64_t *__restrict__ off,
+                                                  const int64_t *__restrict__ soff, const int64_t *__restrict__ toff,
+                                                  const int32_t *__restrict__ blkoff, int ns,
+                                                  const int32_t *__restrict__ mask, const T *__restrict__ rb,
+                                                  const T *__restrict__ twb, T *__restrict__ wsb) {
+    using T2 = typename P2<T>::t;
+    const int s = find_sys2(blkoff, ns, blockIdx.x);
+    if (mask && !mask[s]) return;
+    const PrecDesc &d = pd[s];
     const int64_t t = (int64_t)(blockIdx.x - blkoff[s]) * 256 + threadIdx.x;
     if (t >= d.n_skel) return;
     const T2 *r = reinterpret_cast<const T2 *>(rb + off[s]);
+    const T2 *tw = reinterpret_cast<const T2 *>(twb) + toff[s];
     T *ws = wsb + soff[s];
-    const T *F = reinterpret_cast<const T *>(d.F);
     T2 acc = r[d.skel_dof[t]];
-    for (int32_t e = d.cond_ptr[t]; e < d.cond_ptr[t + 1]; ++e) {
-        const int64_t c = d.cond_cell[e];
-        const int le = d.cond_loc[e];
-        const T *f = F + (c * d.ne + le) * d.n_int;
-        const T2 *ri = r + d.cell_off + c * d.n_int;
-        for (int m = 0; m < d.n_int; ++m) {
-            const T fv = f[m];
-            const T2 rv = ri[m];
-            acc.x -= fv * rv.x;
-            acc.y -= fv * rv.y;
+    if (d.n_int > 0)
+        for (int32_t e = d.cond_ptr[t]; e < d.cond_ptr[t + 1]; ++e) {
+            const T2 v = tw[(int64_t)d.cond_cell[e] * d.ne + d.cond_loc[e]];
+            acc.x -= v.x;
+            acc.y -= v.y;
         }
-    }
     const int32_t p = d.skel_pos[t];
     ws[p] = acc.x;
     ws[d.sp + p] = acc.y;
@@ -609,8 +631,12 @@ __device__ __forceinline__ void bcr_tile(const BcrTask &tk, BcrShared<T, WPB> &s
     }
 }
 
+// waves per SIMD asked of the register allocator (f32: 4, i.e. at most 128 VGPRs)
+template <class T> struct BcrOcc { static constexpr int v = 4; };
+template <> struct BcrOcc<double> { static constexpr int v = 2; };
+
 template <class T, int WPB>
-__global__ void __launch_bounds__(64 * WPB) k_bcr_mfma(const BcrTask *__restrict__ tasks,
+__global__ void __launch_bounds__(64 * WPB, BcrOcc<T>::v) k_bcr_mfma(const BcrTask *__restrict__ tasks,
                                                        const int32_t *__restrict__ blkoff, int ntasks,
                                                        const int32_t *__restrict__ memb_ptr,
                                                        const int32_t *__restrict__ memb,
@@ -658,7 +684,7 @@ __global__ void __launch_bounds__(256) k_cond_bwd(const PrecDesc *__restrict__ p
     using T2 = typename P2<T>::t;
     const int s = find_sys2(blkoff, ns, blockIdx.x);
     if (mask && !mask[s]) return;
-    const PrecDesc d = pd[s];
+    const PrecDesc &d = pd[s];
     const int64_t g = (int64_t)(blockIdx.x - blkoff[s]) * 256 + threadIdx.x;
     if (g >= d.n) return;
     const T *ys = ysb + soff[s];
@@ -675,15 +701,17 @@ __global__ void __launch_bounds__(256) k_cond_bwd(const PrecDesc *__restrict__ p
     const T *Ki = reinterpret_cast<const T *>(d.kiinv) + (c * d.n_int + m) * d.n_int;
     const T2 *ri = r + d.cell_off + c * d.n_int;
     T2 acc{0, 0};
+#pragma unroll 4
     for (int q = 0; q < d.n_int; ++q) {
         acc.x += Ki[q] * ri[q].x;
         acc.y += Ki[q] * ri[q].y;
     }
     const T *F = reinterpret_cast<const T *>(d.F) + c * d.ne * d.n_int;
-    const int32_t *cd = d.cell_dofs + c * d.n_loc;
+    const int32_t *cp = d.cell_pos + c * d.ne;
+#pragma unroll 4
     for (int le = 0; le < d.ne; ++le) {
         const T f = F[le * d.n_int + m];
-        const int32_t p = d.dof_pos[cd[le]];
+        const int32_t p = cp[le];
         acc.x -= f * ys[p];
         acc.y -= f * ys[d.sp + p];
     }
@@ -739,9 +767,10 @@ void launch_repack(const std::vector<RepackDesc> &d, double *dst64, float *dst32
 
 template <class T>
 void launch_prec_apply(const PrecBatch &P, const PrecDesc *d, const int64_t *off, int ns, const int32_t *mask,
-                       const T *r, T *x, T *ws, T *ys, hipStream_t st) {
+                       const T *r, T *x, T *ws, T *ys, T *tw, hipStream_t st) {
+    if (P.cfr.nblocks) k_cond_fr<T><<<P.cfr.nblocks, 256, 0, st>>>(d, off, P.toff.p, P.cfr.blkoff.p, ns, mask, r, tw);
     if (P.skel.nblocks)
-        k_cond_fwd<T><<<P.skel.nblocks, 256, 0, st>>>(d, off, P.soff.p, P.skel.blkoff.p, ns, mask, r, ws);
+        k_cond_fwd<T><<<P.skel.nblocks, 256, 0, st>>>(d, off, P.soff.p, P.toff.p, P.skel.blkoff.p, ns, mask, r, tw, ws);
     launch_bcr_phases<T>(P, mask, ws, ys, st);
     if (P.dofs.nblocks)
         k_cond_bwd<T><<<P.dofs.nblocks, 256, 0, st>>>(d, off, P.soff.p, P.dofs.blkoff.p, ns, mask, r, ys, x);
@@ -749,8 +778,9 @@ void launch_prec_apply(const PrecBatch &P, const PrecDesc *d, const int64_t *off
 }
 
 template void launch_prec_apply<double>(const PrecBatch &, const PrecDesc *, const int64_t *, int, const int32_t *,
-                                        const double *, double *, double *, double *, hipStream_t);
+                                        const double *, double *, double *, double *, double *, hipStream_t);
 template void launch_prec_apply<float>(const PrecBatch &, const PrecDesc *, const int64_t *, int, const int32_t *,
-                                       const float *, float *, float *, float *, hipStream_t);
+                                       const float *, float *, float *, float *, float *, hipStream_t);
+
 
 }  // namespace thm

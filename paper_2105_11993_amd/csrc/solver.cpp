@@ -255,6 +255,7 @@ void Ctx::build(const std::vector<thm_system *> &s, int m, hipStream_t stream) {
         d.cell_dofs = S.cell_dofs.p;
         d.skel_dof = S.Lskel_dof.p;
         d.skel_pos = S.Lskel_pos.p;
+        d.cell_pos = S.Lcell_pos.p;
         d.dof_pos = S.Ldof_pos.p;
         d.cond_ptr = S.Lcond_ptr.p;
         d.cond_cell = S.Lcond_cell.p;
@@ -279,6 +280,19 @@ void Ctx::build(const std::vector<thm_system *> &s, int m, hipStream_t stream) {
     P.Stot = std::max<int64_t>(so, 64);
     P.skel.build(nsk, 256, st);
     P.dofs.build(n, 256, st);
+    {
+        std::vector<int64_t> units(ns), toff(ns);
+        int64_t to = 0;
+        for (int i = 0; i < ns; ++i) {
+            const Topo &t = sys[i]->topo;
+            units[i] = t.n_int > 0 ? (int64_t)t.n_cells * (t.n_loc - t.n_int) : 0;
+            toff[i] = to;
+            to += units[i];
+        }
+        P.cfr.build(units, 256, st);
+        P.toff.upload(toff, st);
+        P.Ttot = std::max<int64_t>(to, 1);
+    }
     {
         std::vector<int32_t> mp(1, 0), mm;
         for (auto &v : members) {
@@ -370,6 +384,7 @@ void Ctx::build(const std::vector<thm_system *> &s, int m, hipStream_t stream) {
     r64.alloc(K.B.Ltot);
     ws64.alloc(P.Stot);
     ys64.alloc(P.Stot);
+    tw64.alloc(2 * P.Ttot);
     THM_HIP(hipMemsetAsync(x64.p, 0, sizeof(double) * x64.n, st));
     THM_HIP(hipMemsetAsync(b64.p, 0, sizeof(double) * b64.n, st));
     THM_HIP(hipMemsetAsync(r64.p, 0, sizeof(double) * r64.n, st));
@@ -391,7 +406,7 @@ KOps<double> Ctx::ops64(float csign) {
         launch_spmv<double>(lpr64, mat64.p, K.B.off.p, sc, ns, mask, x, y, b, csign, st);
     };
     o.prec = [this](const double *x, double *y, const int32_t *mask) {
-        launch_prec_apply<double>(P, P.d64.p, K.B.off.p, ns, mask, x, y, ws64.p, ys64.p, st);
+        launch_prec_apply<double>(P, P.d64.p, K.B.off.p, ns, mask, x, y, ws64.p, ys64.p, tw64.p, st);
     };
     o.graphable = true;
     o.owner = this;
@@ -403,6 +418,7 @@ KOps<float> Ctx::ops32(float csign) {
     if (!ws32.n) {
         ws32.alloc(P.Stot);
         ys32.alloc(P.Stot);
+        tw32.alloc(2 * P.Ttot);
         x32.alloc(K.B.Ltot);
         b32.alloc(K.B.Ltot);
         THM_HIP(hipMemsetAsync(ws32.p, 0, sizeof(float) * ws32.n, st));
@@ -416,7 +432,7 @@ KOps<float> Ctx::ops32(float csign) {
         launch_spmv<float>(lpr32, mat32.p, K.B.off.p, sc, ns, mask, x, y, b, csign, st);
     };
     o.prec = [this](const float *x, float *y, const int32_t *mask) {
-        launch_prec_apply<float>(P, P.d32.p, K.B.off.p, ns, mask, x, y, ws32.p, ys32.p, st);
+        launch_prec_apply<float>(P, P.d32.p, K.B.off.p, ns, mask, x, y, ws32.p, ys32.p, tw32.p, st);
     };
     o.graphable = true;
     o.owner = this;

@@ -76,7 +76,7 @@ struct thm_system {
     thm::DBuf<int32_t> d2c_ptr, d2c_src;
 
     // preconditioner: skeleton maps of this system and the (possibly shared) factor
-    thm::DBuf<int32_t> Lskel_dof, Lskel_pos, Ldof_pos, Lcond_ptr, Lcond_cell, Lcond_loc;
+    thm::DBuf<int32_t> Lskel_dof, Lskel_pos, Ldof_pos, Lcell_pos, Lcond_ptr, Lcond_cell, Lcond_loc;
     std::shared_ptr<thm::Factor> fac;
 
     // domain decomposition
@@ -150,8 +150,8 @@ struct Ctx {
     PrecBatch P;
     DBuf<MatDesc> mat64, mat32;
     DBuf<const uint8_t *> dirs;
-    DBuf<double> x64, b64, r64, ws64, ys64;
-    DBuf<float> x32, b32, ws32, ys32;
+    DBuf<double> x64, b64, r64, ws64, ys64, tw64;
+    DBuf<float> x32, b32, ws32, ys32, tw32;
     DBuf<int32_t> mask_all, run_ir;
     DBuf<double> rnorm, bnorm64, resid64;
     int lpr64 = 81, lpr32 = 81;  // SpMV variants (10 * lanes_per_row + unroll)

@@ -291,6 +291,12 @@ static void assemble_system(thm_system &S, const thm_problem &p, uint32_t iface_
         for (size_t g = 0; g < vpos.size(); ++g)
             if (S.L.dof_pos[g] >= 0) vpos[g] = S.L.skel_pos[S.L.dof_pos[g]];
         S.Ldof_pos.upload(vpos, st);
+        // per cell: padded positions of its skeleton (non-interior) local DoFs
+        const int ne = t.n_loc - t.n_int;
+        std::vector<int32_t> cpos((size_t)t.n_cells * ne);
+        for (int64_t c = 0; c < t.n_cells; ++c)
+            for (int le = 0; le < ne; ++le) cpos[(size_t)c * ne + le] = vpos[t.cell_dofs[(size_t)c * t.n_loc + le]];
+        S.Lcell_pos.upload(cpos, st);
     }
     S.Lcond_ptr.upload(S.L.cond_ptr, st);
     S.Lcond_cell.upload(S.L.cond_cell, st);
