@@ -18,6 +18,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+PRECOND_REPS = 20      # timed applications of the preconditioner (roofline)
+PRECOND_LAUNCHES = 140  # their launches (7 per application on this workload)
 WORKLOAD = ("2D unit square, 256x256 quads, Nedelec degree 2, w=50, kappa=1, mu=1, plane wave on x=0, "
             "impedance elsewhere, 4x4 subdomains, impedance-transmission DDM (interface GMRES), tol 1e-8")
 
@@ -29,11 +31,13 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--mesh", type=int, default=256)
     ap.add_argument("--skip-plain", action="store_true")
-    ap.add_argument("--restart", type=int, default=128)
+    ap.add_argument("--restart", type=int, default=64)
     ap.add_argument("--max-outer", type=int, default=500, help="cap on outer iterations (profiling runs)")
     ap.add_argument("--only-fast", action="store_true", help="time only the batched FP32+refinement form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"),
+                    help="summarize two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this script and exit")
     return ap.parse_args()
 
 
@@ -80,8 +84,90 @@ def cpu_baseline(args, m, outer_iters):
                        f"BLAS threads {cores}")}
 
 
+COPY_MIB = 512  # size of the reference copy (read COPY_MIB, write COPY_MIB)
+
+
+def copy_bandwidth(torch, reps=10):
+    """An elementwise device copy of known size (b = 1 * a, one kernel): the achievable
+    HBM bandwidth reference and the calibration kernel of the FETCH_SIZE / WRITE_SIZE
+    counters (it reads and writes exactly COPY_MIB MiB per launch)."""
+    n = COPY_MIB * 2 ** 20 // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.mul(a, 1.0, out=b)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.mul(a, 1.0, out=b)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"bytes": 2 * 4 * n, "ms": ms, "GBps": 2 * 4 * n / ms / 1e6}
+
+
+def summarize_pmc(fetch_dir, write_dir, out_json):
+    """Per-launch HBM traffic of the cyclic-reduction kernel from two rocprofv3 --pmc runs
+    of this script (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch), each scaled by what the
+    same counter reads for the reference copy.  Only the last PRECOND_REPS applications
+    (the timing loop of thm_time_precond, every member active) are used."""
+    import csv
+    import glob
+    import hashlib
+
+    def load(d, counter):
+        rows = []
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                if r["Counter_Name"] == counter:
+                    rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])))
+        rows.sort()
+        return rows
+
+    res = {}
+    for name, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = load(d, name)
+        copy = [v for _, k, v in rows if "elementwise" in k and v > 0]
+        bcr = [v for _, k, v in rows if "k_bcr_mfma<float" in k]
+        if not copy or not bcr:
+            sys.exit(f"{name}: no calibration or cyclic-reduction dispatches found under {d}")
+        true_kib = COPY_MIB * 1024.0
+        copy_kib = sorted(copy)[len(copy) // 2]
+        factor = true_kib / copy_kib
+        tail = bcr[-PRECOND_LAUNCHES:]
+        res[name] = {"copy_kib_per_launch": copy_kib, "scale": factor,
+                     "bcr_kib_per_launch": sum(tail) / len(tail), "bcr_dispatches": len(tail)}
+    src = os.path.join(ROOT, "paper_2105_11993_amd", "csrc", "kernels_prec.hip")
+    traffic = sum(v["bcr_kib_per_launch"] * 1024.0 * v["scale"] for v in res.values())
+    rec = {"kernel": "k_bcr_mfma<float,4>", "workload": WORKLOAD, "counters": res,
+           "hbm_bytes_per_launch": traffic,
+           "kernels_prec_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest()}
+    with open(out_json, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec, indent=1))
+
+
+def measured_traffic(algorithmic_bytes_per_launch):
+    """HBM bytes per launch of the cyclic-reduction kernel from the committed counter runs
+    (FETCH_SIZE + WRITE_SIZE, calibrated on a copy of known size), if they were taken on
+    the kernel source as it is now; otherwise None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_bcr_mfma_c2_traffic.json")
+    src = os.path.join(ROOT, "paper_2105_11993_amd", "csrc", "kernels_prec.hip")
+    try:
+        rec = json.load(open(path))
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernels_prec_sha256") != digest:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
 def main():
     args = parse()
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not part of "
                                    "this build (the partition would shard one subdomain set per GPU)"}))
@@ -140,7 +226,9 @@ def main():
 
     result_plain = None
     if not args.skip_plain and not args.only_fast:
-        thm.thm_ddm_solve(S, plain, E=E, allow_not_converged=True)  # builds the sequential contexts
+        # one outer iteration builds the sequential contexts (factorisation per subdomain)
+        warm = thm.default_opts(precision=thm.THM_FP64, batched=0, use_graph=0, **dict(common, max_outer=1))
+        thm.thm_ddm_solve(S, warm, E=E, allow_not_converged=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         _, stp = thm.thm_ddm_solve(S, plain, E=E, allow_not_converged=True)
@@ -159,14 +247,17 @@ def main():
     # dominant kernel of the timed solve: the cyclic-reduction multi-GEMV of the batched
     # FP32 subdomain preconditioner (HIP events on the library stream, same launches as
     # inside the solve)
-    ms, by, nl = thm.thm_time_precond(S, thm.THM_FP32_IR, reps=20)
+    ms, by, nl = thm.thm_time_precond(S, thm.THM_FP32_IR, reps=PRECOND_REPS)
     peak = 8000.0
     ach = by / ms / 1e6
-    roof = {"bound": "hbm", "kernel": "k_bcr_gemv<float> (batched FP32 cyclic-reduction multi-GEMV, 16 subdomains, "
-                                      "2 shared factors)",
-            "achieved": ach, "peak": peak, "unit": "GB/s", "frac": ach / peak, "traffic": None,
+    roof = {"bound": "hbm", "kernel": "k_bcr_mfma<float,4> (batched FP32 cyclic-reduction MFMA products, "
+                                      "16 subdomains, 2 shared factors)",
+            "achieved": ach, "peak": peak, "unit": "GB/s", "frac": ach / peak,
+            "traffic": measured_traffic(by / nl),
             "launches_per_apply": nl, "avg_launch_us": ms / nl * 1e3, "bytes_per_apply": by}
     log(args, f"roofline: {roof}")
+    copy = copy_bandwidth(torch)
+    log(args, f"device copy: {copy}")
 
     st = stats[len(stats) // 2]
     out = {
@@ -184,6 +275,7 @@ def main():
         "speedup_vs_plain_fp64": (result_plain["s"] / t_fast) if result_plain else None,
         "spmv": spmv,
         "roofline": roof,
+        "device_copy": copy,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, m, st["outer_iters"])

@@ -137,6 +137,7 @@ constexpr int SEGMAX = 16;   // input segments of one task (the dense last block
 constexpr int BCR_KS = 32;   // columns per MFMA step (4 lane groups x 8 consecutive columns)
 constexpr int BCR_RT = 32;   // rows per block (two 16-row MFMA tiles)
 constexpr int BCR_NM = 16;   // members per block at most (two 16-wide n tiles, re and im columns)
+constexpr int BCR_TAB = 4096;  // 8-column chunks of one task row at most (32768 padded columns)
 struct BcrTask {
     const void *M;             // row-major rows x ld (double or float), 16-byte aligned rows
     int32_t rows, ld, nseg, group;
@@ -149,8 +150,14 @@ struct BcrTask {
     int64_t seg_off[SEGMAX];   // padded position of the segment in a member's work vector
     int64_t out_off;           // padded position of the output block
     int64_t sp;                // planar half-stride of the group's work vectors
+    // per 8-column chunk kc (ld / 8 entries): 2 (p - 8 kc) + src, where p is the position
+    // of column 8 kc in a member's work vector and src selects ws (0) or ys (1); chunks
+    // past the padded width repeat the last chunk of the last segment (zero in M)
+    const int32_t *tab;
 };
-constexpr int bcr_wpb(int prec) { return prec ? 4 : 4; }  // waves per block (FP32, FP64): the column split
+// chunk table entries of one task (host side, see BcrTask::tab)
+void bcr_chunk_table(const BcrTask &t, std::vector<int32_t> &out);
+constexpr int BCR_WPB = 4;   // waves per block: the column split of a row tile
 
 // Copy of one apply matrix into the padded layout (setup only).
 struct RepackDesc {
@@ -163,6 +170,7 @@ void launch_repack(const std::vector<RepackDesc> &d, double *dst64, float *dst32
 
 struct PrecPhase {
     DBuf<BcrTask> tasks[2];    // FP64, FP32 matrices
+    DBuf<int32_t> tab;         // chunk tables of the tasks
     Sched sched[2];            // blocks = row blocks x member chunks
     int ntasks = 0;
 };

@@ -500,12 +500,14 @@ __device__ __forceinline__ void load8(const T *p, T (&v)[8]) {
     }
 }
 
+
 template <class T, int WPB>
 struct BcrShared {
-    T red[WPB][2 * BCR_NM][BCR_RT + 4];  // partial tiles: [wave][n][row]
-    int32_t pstart[SEGMAX + 1];
-    int32_t src[SEGMAX];
-    int64_t delta[SEGMAX];               // segment position in the vector minus its first column
+    T red[WPB / 2][2 * BCR_NM][BCR_RT + 4];  // partial tiles: [wave pair][n][row]
+    // per 8-column chunk kc: position of column 8 kc in a member's vector minus 8 kc,
+    // times 2, plus the source (0 = ws, 1 = ys); chunks past the padded width repeat
+    // the last chunk of the last segment (zero in M)
+    int32_t tab[BCR_TAB];
 };
 
 // Operands of one 32-column step: 8 columns of two M rows and of NNT X columns per lane.
@@ -514,35 +516,20 @@ struct BcrStep {
     T a0[8], a1[8], b[NNT][8];
 };
 
-// Lane-private walk over the input segments.  bseg[nt] + k addresses column k of the
-// lane's X column; columns past the padded width (zero in M) read the last 8 columns
-// of the last segment instead, and lanes of absent members read the chunk's first
-// member (their output columns are never stored), so every load is in bounds and
-// every value that meets a nonzero M entry is the right one.
+// Loads of one step; branch-free so that the next step's loads stay in flight while
+// the current step's MFMAs run.  Lanes of absent members read the chunk's first
+// member (their output columns are never stored).
 template <class T, int WPB, int NNT>
-struct BcrWalk {
-    int sg = 0, nextb = 0;
-    const T *bseg[NNT];
-    __device__ __forceinline__ void enter(const BcrTask &tk, const BcrShared<T, WPB> &sh, const int64_t (&bbase)[NNT],
-                                          int k, const T *wsb, const T *ysb) {
-        while (sg + 1 < tk.nseg && k >= sh.pstart[sg + 1]) ++sg;
-        nextb = sg + 1 < tk.nseg ? sh.pstart[sg + 1] : 0x7fffffff;
-        const T *src = sh.src[sg] ? ysb : wsb;
-#pragma unroll
-        for (int nt = 0; nt < NNT; ++nt) bseg[nt] = src + bbase[nt] + sh.delta[sg];
-    }
-};
-
-template <class T, int WPB, int NNT>
-__device__ __forceinline__ void bcr_fetch(BcrStep<T, NNT> &o, BcrWalk<T, WPB, NNT> &w, const BcrTask &tk,
-                                          const BcrShared<T, WPB> &sh, const int64_t (&bbase)[NNT], const T *A0,
-                                          const T *A1, int k, int kvalid, const T *wsb, const T *ysb) {
+__device__ __forceinline__ void bcr_fetch(BcrStep<T, NNT> &o, const BcrShared<T, WPB> &sh,
+                                          const int64_t (&bbase)[NNT], const T *A0, const T *A1, int k,
+                                          const T *wsb, const T *ysb) {
     load8(A0 + k, o.a0);
     load8(A1 + k, o.a1);
-    if (k >= w.nextb) w.enter(tk, sh, bbase, k, wsb, ysb);
-    const int kk = k < kvalid ? k : kvalid - 8;
+    const int32_t e = sh.tab[(k >> 3) + ((threadIdx.x >> 4) & 3)];  // this lane group's chunk
+    const T *src = (e & 1) ? ysb : wsb;
+    const int64_t pos = (int64_t)(e >> 1) + k;
 #pragma unroll
-    for (int nt = 0; nt < NNT; ++nt) load8(w.bseg[nt] + kk, o.b[nt]);
+    for (int nt = 0; nt < NNT; ++nt) load8(src + bbase[nt] + pos, o.b[nt]);
 }
 
 template <class T, int NNT>
@@ -567,13 +554,13 @@ __device__ __forceinline__ void bcr_tile(const BcrTask &tk, BcrShared<T, WPB> &s
     const T *M = static_cast<const T *>(tk.M);
     const int64_t ld = tk.ld;
     // rows past the end load the last row again; their results are dropped
-    const T *A0 = M + min(row0 + i16, tk.rows - 1) * ld;
-    const T *A1 = M + min(row0 + 16 + i16, tk.rows - 1) * ld;
+    const T *A0 = M + min(row0 + i16, tk.rows - 1) * ld + 8 * g;
+    const T *A1 = M + min(row0 + 16 + i16, tk.rows - 1) * ld + 8 * g;
     int64_t bbase[NNT];
 #pragma unroll
     for (int nt = 0; nt < NNT; ++nt) {
         const int mi = mb + 8 * nt + (i16 >> 1);
-        bbase[nt] = soff[memb[mi < m1 ? mi : mb]] + (i16 & 1) * tk.sp;
+        bbase[nt] = soff[memb[mi < m1 ? mi : mb]] + (i16 & 1) * tk.sp + 8 * g;
     }
     V4 acc[2][NNT];
 #pragma unroll
@@ -581,37 +568,51 @@ __device__ __forceinline__ void bcr_tile(const BcrTask &tk, BcrShared<T, WPB> &s
 #pragma unroll
         for (int nt = 0; nt < NNT; ++nt) acc[mt][nt] = V4{0, 0, 0, 0};
     const int kbeg = wave * tk.kq;
-    const int kend = min(tk.ld, kbeg + tk.kq);
-    const int kvalid = sh.pstart[tk.nseg];
-    if (kbeg < kend) {
-        // two operand buffers in turn: the loads of the next step are in flight while
-        // the MFMAs of the current one run
-        BcrWalk<T, WPB, NNT> w;
-        w.enter(tk, sh, bbase, kbeg + 8 * g, wsb, ysb);
+    const int nst = max(0, (min(tk.ld, kbeg + tk.kq) - kbeg) / BCR_KS);  // same for the whole wave
+    if (nst > 0) {
+        // two operand buffers in turn; the prefetch past the last step repeats the last
+        // step's addresses
         BcrStep<T, NNT> p, q;
-        int k = kbeg + 8 * g;
-        bcr_fetch(p, w, tk, sh, bbase, A0, A1, k, kvalid, wsb, ysb);
-        for (int k0 = kbeg;;) {
-            if (k0 + BCR_KS < kend) bcr_fetch(q, w, tk, sh, bbase, A0, A1, k + BCR_KS, kvalid, wsb, ysb);
+        const int klast = kbeg + (nst - 1) * BCR_KS;
+        bcr_fetch<T, WPB, NNT>(p, sh, bbase, A0, A1, kbeg, wsb, ysb);
+        // (the scheduling barriers keep the prefetch ahead of the MFMAs it overlaps)
+        for (int st = 0;; st += 2) {
+            bcr_fetch<T, WPB, NNT>(q, sh, bbase, A0, A1, min(kbeg + (st + 1) * BCR_KS, klast), wsb, ysb);
+            __builtin_amdgcn_sched_barrier(0);
             bcr_mma(p, acc);
-            k0 += BCR_KS;
-            k += BCR_KS;
-            if (k0 >= kend) break;
-            if (k0 + BCR_KS < kend) bcr_fetch(p, w, tk, sh, bbase, A0, A1, k + BCR_KS, kvalid, wsb, ysb);
+            if (st + 1 >= nst) break;
+            bcr_fetch<T, WPB, NNT>(p, sh, bbase, A0, A1, min(kbeg + (st + 2) * BCR_KS, klast), wsb, ysb);
+            __builtin_amdgcn_sched_barrier(0);
             bcr_mma(q, acc);
-            k0 += BCR_KS;
-            k += BCR_KS;
-            if (k0 >= kend) break;
+            if (st + 2 >= nst) break;
         }
     }
-    // accumulator v: row Mfma::row(g, v) of m tile mt, column i16 of n tile nt
+    // Sum of the waves' partial tiles in a fixed order: the upper half of the waves
+    // store, the lower half adds and stores, then every thread sums the WPB/2 slots.
+    // Accumulator v of lane (i16, g) is row Mfma::row(g, v) of m tile mt, column i16
+    // of n tile nt.
+    constexpr int H = WPB / 2;
+    if (wave >= H) {
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
+        for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-        for (int nt = 0; nt < NNT; ++nt)
+            for (int nt = 0; nt < NNT; ++nt)
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-                sh.red[wave][16 * nt + i16][16 * mt + Mfma<T>::row(g, v)] = acc[mt][nt][v];
+                for (int v = 0; v < 4; ++v)
+                    sh.red[wave - H][16 * nt + i16][16 * mt + Mfma<T>::row(g, v)] = acc[mt][nt][v];
+    }
+    __syncthreads();
+    if (wave < H) {
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < NNT; ++nt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    T &slot = sh.red[wave][16 * nt + i16][16 * mt + Mfma<T>::row(g, v)];
+                    slot = acc[mt][nt][v] + slot;
+                }
+    }
     __syncthreads();
     constexpr int NOUT = BCR_RT * 16 * NNT;
     for (int o = threadIdx.x; o < NOUT; o += 64 * WPB) {
@@ -622,7 +623,7 @@ __device__ __forceinline__ void bcr_tile(const BcrTask &tk, BcrShared<T, WPB> &s
         if (mask && !mask[s]) continue;
         T v = 0;
 #pragma unroll
-        for (int w = 0; w < WPB; ++w) v += sh.red[w][n][r];
+        for (int w = 0; w < H; ++w) v += sh.red[w][n][r];
         T *y = (tk.out_dst ? ysb : wsb) + soff[s] + (n & 1) * tk.sp + tk.out_off + row0 + r;
         if (tk.subtract)
             *y -= v;
@@ -660,14 +661,7 @@ __global__ void __launch_bounds__(64 * WPB, BcrOcc<T>::v) k_bcr_mfma(const BcrTa
     for (int j = 0; j < 8 * tk.nnt; ++j)
         if (mb + j < m1 && (!mask || mask[memb[mb + j]])) any = true;
     if (!any) return;  // same decision in every thread of the block
-    if (threadIdx.x <= SEGMAX) {
-        const int j = threadIdx.x;
-        sh.pstart[j] = j <= tk.nseg ? tk.seg_pstart[j] : tk.seg_pstart[tk.nseg];
-        if (j < SEGMAX) {
-            sh.src[j] = tk.seg_src[j];
-            sh.delta[j] = j < tk.nseg ? tk.seg_off[j] - tk.seg_pstart[j] : 0;
-        }
-    }
+    for (int kc = threadIdx.x; kc < (tk.ld >> 3); kc += blockDim.x) sh.tab[kc] = tk.tab[kc];
     __syncthreads();
     if (tk.nnt == 1)
         bcr_tile<T, WPB, 1>(tk, sh, rt * BCR_RT, mb, m1, memb, soff, mask, wsb, ysb);
@@ -721,11 +715,12 @@ __global__ void __launch_bounds__(256) k_cond_bwd(const PrecDesc *__restrict__ p
 template <class T>
 void launch_bcr_phases(const PrecBatch &P, const int32_t *mask, T *ws, T *ys, hipStream_t st) {
     constexpr int prec = sizeof(T) == 8 ? 0 : 1;
-    constexpr int wpb = bcr_wpb(prec);
-    for (const PrecPhase &ph : P.phases)
-        if (ph.sched[prec].nblocks)
-            k_bcr_mfma<T, wpb><<<ph.sched[prec].nblocks, 64 * wpb, 0, st>>>(
-                ph.tasks[prec].p, ph.sched[prec].blkoff.p, ph.ntasks, P.memb_ptr.p, P.memb.p, P.soff.p, mask, ws, ys);
+    for (const PrecPhase &ph : P.phases) {
+        const int nb = ph.sched[prec].nblocks;
+        if (!nb) continue;
+        k_bcr_mfma<T, BCR_WPB><<<nb, 64 * BCR_WPB, 0, st>>>(ph.tasks[prec].p, ph.sched[prec].blkoff.p, ph.ntasks,
+                                                          P.memb_ptr.p, P.memb.p, P.soff.p, mask, ws, ys);
+    }
     THM_HIP(hipGetLastError());
 }
 template void launch_bcr_phases<double>(const PrecBatch &, const int32_t *, double *, double *, hipStream_t);

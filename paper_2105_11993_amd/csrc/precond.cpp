@@ -161,6 +161,8 @@ static void plan(Factor &f) {
         }
         b.seg_pstart[b.nseg] = c;
         b.ld = (c + BCR_KS - 1) / BCR_KS * BCR_KS;
+        if (b.ld > 8 * BCR_TAB)
+            fail(THM_EUNSUPPORTED, "a cyclic-reduction block has more columns than the apply kernel supports");
         b.poff = poff;
         poff += (int64_t)b.rows * b.ld;
     };

@@ -208,20 +208,65 @@ template void gmres_run<double>(Krylov &, const KOps<double> &, const double *, 
 template void gmres_run<float>(Krylov &, const KOps<float> &, const float *, float *, const int32_t *,
                                const GmresParams &, hipStream_t);
 
+void bcr_chunk_table(const BcrTask &t, std::vector<int32_t> &out) {
+    const int nch = t.ld / 8, nvalid = t.seg_pstart[t.nseg] / 8;
+    out.assign(nch, 0);
+    int q = 0;
+    for (int kc = 0; kc < nch; ++kc) {
+        const int kk = std::min(kc, nvalid - 1);
+        while (q + 1 < t.nseg && 8 * kk >= t.seg_pstart[q + 1]) ++q;
+        // column 8 kc reads position seg_off + (8 kk - pstart) = delta + 8 kc
+        const int64_t delta = t.seg_off[q] - t.seg_pstart[q] + 8 * (int64_t)(kk - kc);
+        if (2 * delta > INT32_MAX || 2 * delta < INT32_MIN)
+            fail(THM_EUNSUPPORTED, "skeleton work vector too long for the apply kernel");
+        out[kc] = (int32_t)(2 * delta) | (t.seg_src[q] & 1);
+    }
+}
+
 // ------------------------------------------------------------------ batched context
 void Ctx::build(const std::vector<thm_system *> &s, int m, hipStream_t stream) {
     sys = s;
     ns = (int)s.size();
     st = stream;
+    std::vector<int64_t> n(ns);
+    for (int i = 0; i < ns; ++i) n[i] = sys[i]->n;
+    K.init(n, m, st);
+    std::vector<MatDesc> h64(ns), h32(ns);
+    std::vector<const uint8_t *> hd(ns);
+    for (int i = 0; i < ns; ++i) {
+        const thm_system &S = *sys[i];
+        h64[i] = {S.n, S.k_rowptr.p, S.k_col.p, S.kval.p, S.c_rowptr.p, S.c_col.p, S.cval.p};
+        h32[i] = {S.n, S.k_rowptr.p, S.k_col.p, S.kval32.p, S.c_rowptr.p, S.c_col.p, S.cval32.p};
+        hd[i] = S.dir_d.p;
+    }
+    mat64.upload(h64, st);
+    mat32.upload(h32, st);
+    dirs.upload(hd, st);
+    x64.alloc(K.B.Ltot);
+    b64.alloc(K.B.Ltot);
+    r64.alloc(K.B.Ltot);
+    THM_HIP(hipMemsetAsync(x64.p, 0, sizeof(double) * x64.n, st));
+    THM_HIP(hipMemsetAsync(b64.p, 0, sizeof(double) * b64.n, st));
+    THM_HIP(hipMemsetAsync(r64.p, 0, sizeof(double) * r64.n, st));
+    mask_all.upload(std::vector<int32_t>(ns, 1), st);
+    run_ir.alloc(ns);
+    rnorm.alloc(ns);
+    bnorm64.alloc(ns);
+    resid64.alloc(ns);
+    THM_HIP(hipStreamSynchronize(st));
+    autotune();
+}
+
+// Preconditioner of the batch: factorisation (shared between identical systems) and the
+// batched apply schedule.  Built on first use, so SpMV-only uses of a context skip it.
+void Ctx::build_prec() {
+    if (prec_ready) return;
     setup_precond(sys, st);
     std::vector<int64_t> n(ns), nsk(ns);
     for (int i = 0; i < ns; ++i) {
         n[i] = sys[i]->n;
         nsk[i] = sys[i]->L.n_skel;
     }
-    K.init(n, m, st);
-    std::vector<MatDesc> h64(ns), h32(ns);
-    std::vector<const uint8_t *> hd(ns);
     std::vector<PrecDesc> p64(ns), p32(ns);
     std::vector<int64_t> soff(ns);
     // factor groups in order of first appearance
@@ -238,9 +283,6 @@ void Ctx::build(const std::vector<thm_system *> &s, int m, hipStream_t stream) {
         } else {
             members[it - groups.begin()].push_back(i);
         }
-        h64[i] = {S.n, S.k_rowptr.p, S.k_col.p, S.kval.p, S.c_rowptr.p, S.c_col.p, S.cval.p};
-        h32[i] = {S.n, S.k_rowptr.p, S.k_col.p, S.kval32.p, S.c_rowptr.p, S.c_col.p, S.cval32.p};
-        hd[i] = S.dir_d.p;
         const Topo &t = S.topo;
         PrecDesc d{};
         d.n = S.n;
@@ -270,9 +312,6 @@ void Ctx::build(const std::vector<thm_system *> &s, int m, hipStream_t stream) {
         so += 2 * S.L.n_skel_pad;  // planar: real block, then imaginary block
         so = (so + 63) & ~int64_t(63);
     }
-    mat64.upload(h64, st);
-    mat32.upload(h32, st);
-    dirs.upload(hd, st);
     P.ns = ns;
     P.d64.upload(p64, st);
     P.d32.upload(p32, st);
@@ -312,8 +351,7 @@ void Ctx::build(const std::vector<thm_system *> &s, int m, hipStream_t stream) {
         t.ld = b.ld;
         t.nseg = b.nseg;
         t.group = g;
-        const int wpb = bcr_wpb(prec);
-        t.kq = ((b.ld + wpb - 1) / wpb + BCR_KS - 1) / BCR_KS * BCR_KS;
+        t.kq = ((b.ld + BCR_WPB - 1) / BCR_WPB + BCR_KS - 1) / BCR_KS * BCR_KS;
         const int nm = (int)members[g].size();
         t.nnt = nm > 8 ? 2 : 1;
         t.nmc = (nm + 8 * t.nnt - 1) / (8 * t.nnt);
@@ -355,6 +393,18 @@ void Ctx::build(const std::vector<thm_system *> &s, int m, hipStream_t stream) {
         P.phases.emplace_back();
         PrecPhase &ph = P.phases.back();
         ph.ntasks = (int)t64.size();
+        {
+            // chunk tables (the same for both precisions)
+            std::vector<int32_t> all, one;
+            std::vector<int64_t> at;
+            for (const BcrTask &t : t64) {
+                at.push_back((int64_t)all.size());
+                bcr_chunk_table(t, one);
+                all.insert(all.end(), one.begin(), one.end());
+            }
+            ph.tab.upload(all, st);
+            for (size_t i = 0; i < t64.size(); ++i) t64[i].tab = t32[i].tab = ph.tab.p + at[i];
+        }
         ph.tasks[0].upload(t64, st);
         ph.tasks[1].upload(t32, st);
         ph.sched[0].build(u64, 1, st);
@@ -379,33 +429,24 @@ void Ctx::build(const std::vector<thm_system *> &s, int m, hipStream_t stream) {
                 for (const auto &b : f.bwd[lev]) v.push_back(&b);
             return v;
         });
-    x64.alloc(K.B.Ltot);
-    b64.alloc(K.B.Ltot);
-    r64.alloc(K.B.Ltot);
     ws64.alloc(P.Stot);
     ys64.alloc(P.Stot);
     tw64.alloc(2 * P.Ttot);
-    THM_HIP(hipMemsetAsync(x64.p, 0, sizeof(double) * x64.n, st));
-    THM_HIP(hipMemsetAsync(b64.p, 0, sizeof(double) * b64.n, st));
-    THM_HIP(hipMemsetAsync(r64.p, 0, sizeof(double) * r64.n, st));
     THM_HIP(hipMemsetAsync(ws64.p, 0, sizeof(double) * ws64.n, st));
     THM_HIP(hipMemsetAsync(ys64.p, 0, sizeof(double) * ys64.n, st));
-    mask_all.upload(std::vector<int32_t>(ns, 1), st);
-    run_ir.alloc(ns);
-    rnorm.alloc(ns);
-    bnorm64.alloc(ns);
-    resid64.alloc(ns);
     THM_HIP(hipStreamSynchronize(st));
-    autotune();
+    prec_ready = true;
 }
 
-KOps<double> Ctx::ops64(float csign) {
+KOps<double> Ctx::ops64(float csign, bool with_prec) {
+    if (with_prec) build_prec();
     KOps<double> o;
     o.apply = [this, csign](const double *x, double *y, const double *b, const int32_t *mask) {
         const Sched &sc = K.B.spmv_sched(lpr64, st);
         launch_spmv<double>(lpr64, mat64.p, K.B.off.p, sc, ns, mask, x, y, b, csign, st);
     };
     o.prec = [this](const double *x, double *y, const int32_t *mask) {
+        if (!prec_ready) fail(THM_EINVAL, "preconditioner used before it was built");
         launch_prec_apply<double>(P, P.d64.p, K.B.off.p, ns, mask, x, y, ws64.p, ys64.p, tw64.p, st);
     };
     o.graphable = true;
@@ -414,17 +455,22 @@ KOps<double> Ctx::ops64(float csign) {
     return o;
 }
 
-KOps<float> Ctx::ops32(float csign) {
-    if (!ws32.n) {
-        ws32.alloc(P.Stot);
-        ys32.alloc(P.Stot);
-        tw32.alloc(2 * P.Ttot);
+KOps<float> Ctx::ops32(float csign, bool with_prec) {
+    if (!x32.n) {
         x32.alloc(K.B.Ltot);
         b32.alloc(K.B.Ltot);
-        THM_HIP(hipMemsetAsync(ws32.p, 0, sizeof(float) * ws32.n, st));
-        THM_HIP(hipMemsetAsync(ys32.p, 0, sizeof(float) * ys32.n, st));
         THM_HIP(hipMemsetAsync(x32.p, 0, sizeof(float) * x32.n, st));
         THM_HIP(hipMemsetAsync(b32.p, 0, sizeof(float) * b32.n, st));
+    }
+    if (with_prec) {
+        build_prec();
+        if (!ws32.n) {
+            ws32.alloc(P.Stot);
+            ys32.alloc(P.Stot);
+            tw32.alloc(2 * P.Ttot);
+            THM_HIP(hipMemsetAsync(ws32.p, 0, sizeof(float) * ws32.n, st));
+            THM_HIP(hipMemsetAsync(ys32.p, 0, sizeof(float) * ys32.n, st));
+        }
     }
     KOps<float> o;
     o.apply = [this, csign](const float *x, float *y, const float *b, const int32_t *mask) {
@@ -432,6 +478,7 @@ KOps<float> Ctx::ops32(float csign) {
         launch_spmv<float>(lpr32, mat32.p, K.B.off.p, sc, ns, mask, x, y, b, csign, st);
     };
     o.prec = [this](const float *x, float *y, const int32_t *mask) {
+        if (!ws32.n) fail(THM_EINVAL, "preconditioner used before it was built");
         launch_prec_apply<float>(P, P.d32.p, K.B.off.p, ns, mask, x, y, ws32.p, ys32.p, tw32.p, st);
     };
     o.graphable = true;
@@ -510,6 +557,7 @@ void Ctx::solve(const thm_solve_opts &o, float csign, const int32_t *mask, std::
 }
 
 double Ctx::time_bcr(int prec, int reps, double *bytes, int *launches) {
+    build_prec();
     if (prec) ops32(1.f);
     hipEvent_t e0, e1;
     THM_HIP(hipEventCreate(&e0));
@@ -614,7 +662,7 @@ void Ctx::autotune() {
         });
         if (ms < best) { best = ms; lpr64 = c; }
     }
-    ops32(1.f);
+    ops32(1.f, false);
     best = 1e30f;
     for (int c : cand) {
         const Sched &sc = K.B.spmv_sched(c, st);

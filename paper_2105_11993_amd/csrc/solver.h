@@ -156,15 +156,19 @@ struct Ctx {
     DBuf<double> rnorm, bnorm64, resid64;
     int lpr64 = 81, lpr32 = 81;  // SpMV variants (10 * lanes_per_row + unroll)
 
+    bool prec_ready = false;
+
     void build(const std::vector<thm_system *> &s, int m, hipStream_t stream);
-    KOps<double> ops64(float csign);
-    KOps<float> ops32(float csign);
+    void build_prec();
+    // operator (and, unless with_prec is false, preconditioner) of the batch
+    KOps<double> ops64(float csign, bool with_prec = true);
+    KOps<float> ops32(float csign, bool with_prec = true);
     // Solve A x = b for the systems in mask (device, nullable = all); b64/x64 slots hold
     // the right-hand sides and initial guesses (zero on Dirichlet rows).
     void solve(const thm_solve_opts &o, float csign, const int32_t *mask, std::vector<int> &iters,
                std::vector<int> &refines, std::vector<double> &resid);
     void autotune();
-    // Time `reps` applications of the cyclic-reduction phases (k_bcr_gemv launches only)
+    // Time `reps` applications of the cyclic-reduction phases (k_bcr_mfma launches only)
     // with HIP events on this context's stream; returns ms per application, and the
     // algorithmic bytes and number of launches per application.
     double time_bcr(int prec, int reps, double *bytes, int *launches);

@@ -1047,12 +1047,12 @@ thm_status thm_apply_operator(thm_system *sys, int32_t transpose, int32_t precis
         c.copy_in(0, (const double *)x_dev, c.x64.p);
         const float sg = transpose ? -1.f : 1.f;
         if (precision == THM_FP32_IR) {
-            KOps<float> o = c.ops32(sg);
+            KOps<float> o = c.ops32(sg, false);
             launch_scale<double, float>(c.K.B, nullptr, nullptr, 0, c.x64.p, c.x32.p, nullptr, 0, nullptr, c.st);
             o.apply(c.x32.p, c.b32.p, nullptr, nullptr);
             launch_scale<float, double>(c.K.B, nullptr, nullptr, 0, c.b32.p, c.r64.p, nullptr, 0, nullptr, c.st);
         } else {
-            c.ops64(sg).apply(c.x64.p, c.r64.p, nullptr, nullptr);
+            c.ops64(sg, false).apply(c.x64.p, c.r64.p, nullptr, nullptr);
         }
         c.copy_out(0, c.r64.p, (double *)y_dev);
         stream_join(c.st, us);
@@ -1125,8 +1125,8 @@ thm_status thm_time_spmv(thm_system *sys, int32_t precision, int32_t reps, doubl
         THM_HIP(hipEventCreate(&e0));
         THM_HIP(hipEventCreate(&e1));
         const bool f32 = precision == THM_FP32_IR;
-        KOps<double> o64 = c.ops64(1.f);
-        KOps<float> o32 = c.ops32(1.f);
+        KOps<double> o64 = c.ops64(1.f, false);
+        KOps<float> o32 = c.ops32(1.f, false);
         auto once = [&] {
             if (f32) o32.apply(c.x32.p, c.b32.p, nullptr, nullptr);
             else o64.apply(c.x64.p, c.r64.p, nullptr, nullptr);
