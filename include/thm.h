@@ -113,7 +113,7 @@ typedef struct {
     int64_t n_interface;     /* complex interface unknowns of the DDM (sum over directed interfaces; -1 before
                                 the first DDM solve) */
     int32_t spmv_variant;    /* autotuned FP64 SpMV variant of this system's context (10 x lanes per row +
-                                unroll), -1 before the first solve */
+                                unroll for CSR-vector, 19 for SELL-64), -1 before the first solve */
 } thm_info;
 
 typedef struct thm_system thm_system;
@@ -198,6 +198,17 @@ thm_status thm_export_elements(thm_system *sys, int64_t c0, int64_t count, doubl
  * measured with HIP events on `stream`; bytes_out: algorithmic bytes per launch. */
 thm_status thm_time_spmv(thm_system *sys, int32_t precision, int32_t reps, double *ms_out,
                          double *bytes_out, void *stream);
+
+/* Block SpMV variants of eq. (4)'s operator: CSR-vector with L lanes per row and unroll U
+ * (code 10 L + U, L in {2, 4, 8, 16, 32, 64}, U in {1, 4}; L = 64 only with U = 1) or
+ * SELL-64 (code 19: one wave per slice of 64 rows, column-major padded entries). */
+#define THM_SPMV_SELL 19
+
+/* Pin the SpMV variant of the single-system context of `sys` (the one used by
+ * thm_gmres_solve on {sys}, thm_apply_operator and thm_time_spmv), overriding the
+ * autotuner's choice for that precision; variant = -1 re-runs the autotuner.  Returns
+ * THM_EINVAL for an unknown variant or precision. */
+thm_status thm_set_spmv_variant(thm_system *sys, int32_t precision, int32_t variant);
 
 /* Average device time (ms) of `reps` applications of the block cyclic-reduction
  * phases of the preconditioner (eq. (11)) -- the DDM's batched subdomain context if a

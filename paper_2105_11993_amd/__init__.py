@@ -60,7 +60,9 @@ class ThmInfo(ctypes.Structure):
 EXPORTS = ["thm_default_opts", "thm_assemble", "thm_gmres_solve", "thm_ddm_solve", "thm_adjoint_grad",
            "thm_system_info", "thm_system_set_mu", "thm_system_destroy", "thm_last_error", "thm_apply_operator",
            "thm_apply_precond", "thm_export_matrices", "thm_export_rhs", "thm_export_elements", "thm_time_spmv",
-           "thm_time_precond"]
+           "thm_time_precond", "thm_set_spmv_variant"]
+THM_SPMV_SELL = 19
+SPMV_VARIANTS = [21, 41, 81, 161, 321, 641, 24, 44, 84, 164, 324, THM_SPMV_SELL]
 
 
 def load_library(path=LIB_PATH):
@@ -86,6 +88,7 @@ def load_library(path=LIB_PATH):
         "thm_export_elements": (i32, [vp, i64, i64, vp]),
         "thm_time_spmv": (i32, [vp, i32, i32, dp, dp, vp]),
         "thm_time_precond": (i32, [vp, i32, i32, dp, dp, ctypes.POINTER(i32), vp]),
+        "thm_set_spmv_variant": (i32, [vp, i32, i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -311,6 +314,11 @@ def thm_time_spmv(system, precision=THM_FP64, reps=20, stream=None):
     _check(_lib.thm_time_spmv(system.handle, int(precision), int(reps), ctypes.byref(ms), ctypes.byref(by),
                               _stream(stream)))
     return ms.value, by.value
+
+
+def thm_set_spmv_variant(system, precision, variant):
+    """Pin the SpMV variant of the system's own context (-1: autotune again)."""
+    _check(_lib.thm_set_spmv_variant(system.handle, int(precision), int(variant)))
 
 
 def thm_time_precond(system, precision=THM_FP64, reps=20, stream=None):

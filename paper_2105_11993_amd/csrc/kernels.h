@@ -15,7 +15,18 @@ struct MatDesc {
     const void *kval;
     const int32_t *crowptr, *ccol;
     const void *cval;
+    // K in SELL-64 (slices of 64 consecutive rows, entries column-major within a slice,
+    // padded to the longest row of the slice with zero values): the same values as kval
+    const int32_t *sl_ptr, *sl_col;  // entry offset of each slice (n_slices + 1); columns
+    const void *sl_val;
 };
+constexpr int SELL_C = 64;        // rows per slice (one wave, one row per lane)
+constexpr int SPMV_SELL = 19;     // SpMV variant code of the SELL-64 kernel (256 rows per block)
+// Host: SELL-64 layout of a CSR pattern; src[e] = CSR index of entry e, or -1 (padding).
+void sell_build(int64_t n, const std::vector<int32_t> &rowptr, const std::vector<int32_t> &col,
+                std::vector<int32_t> &ptr, std::vector<int32_t> &scol, std::vector<int32_t> &src);
+// Device: SELL values from the CSR values (FP64 and FP32 copies).
+void launch_sell_fill(int64_t ne, const int32_t *src, const double *kval, double *v64, float *v32, hipStream_t st);
 
 // Flattened block schedule: block b belongs to system s with blkoff[s] <= b < blkoff[s+1].
 // The device array holds blkoff[0..ns] followed by the block -> system map, so a kernel
@@ -171,6 +182,7 @@ void launch_repack(const std::vector<RepackDesc> &d, double *dst64, float *dst32
 struct PrecPhase {
     DBuf<BcrTask> tasks[2];    // FP64, FP32 matrices
     DBuf<int32_t> tab;         // chunk tables of the tasks
+    int max_ld = 0;            // widest task (padded columns)
     Sched sched[2];            // blocks = row blocks x member chunks
     int ntasks = 0;
 };

@@ -110,7 +110,88 @@ __global__ void __launch_bounds__(256) k_spmv(const MatDesc *__restrict__ mats, 
     }
 }
 
-// Variant code v = 10 * lanes_per_row + unroll (unroll 1 or 4), chosen by the autotuner.
+// SELL-64 variant: one wave per slice of 64 rows, one row per lane.  The value and
+// column loads of a wave are 64 consecutive entries (coalesced), there is no cross-lane
+// reduction and no divergence inside the K loop; padding entries have value 0 and point
+// at a valid column.  The boundary operator C (few rows) is applied from its CSR.
+template <class T>
+__global__ void __launch_bounds__(256) k_spmv_sell(const MatDesc *__restrict__ mats, const int64_t *__restrict__ off,
+                                                   const int32_t *__restrict__ blkoff, int ns,
+                                                   const int32_t *__restrict__ mask, const T *__restrict__ xb,
+                                                   T *__restrict__ yb, const T *__restrict__ bb, float csign) {
+    using T2 = typename V2<T>::t;
+    const int s = find_sys(blkoff, ns, blockIdx.x);
+    if (mask && !mask[s]) return;
+    const MatDesc &m = mats[s];
+    const int64_t slice = (int64_t)(blockIdx.x - blkoff[s]) * 4 + (threadIdx.x >> 6);
+    if (slice * SELL_C >= m.n) return;  // whole wave
+    const int lane = threadIdx.x & 63;
+    const int64_t row = slice * SELL_C + lane;
+    const T2 *x = reinterpret_cast<const T2 *>(xb + off[s]);
+    const int32_t e0 = m.sl_ptr[slice], w = (m.sl_ptr[slice + 1] - e0) / SELL_C;
+    const int32_t *cp = m.sl_col + e0 + lane;
+    const T *vp = reinterpret_cast<const T *>(m.sl_val) + e0 + lane;
+    T ar = 0, ai = 0;
+    int k = 0;
+    for (; k + 4 <= w; k += 4) {
+        int32_t c[4];
+        T v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            c[u] = cp[(k + u) * SELL_C];
+            v[u] = vp[(k + u) * SELL_C];
+        }
+        T2 xv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) xv[u] = x[c[u]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            ar += v[u] * xv[u].x;
+            ai += v[u] * xv[u].y;
+        }
+    }
+    for (; k < w; ++k) {
+        const T v = vp[k * SELL_C];
+        const T2 xv = x[cp[k * SELL_C]];
+        ar += v * xv.x;
+        ai += v * xv.y;
+    }
+    if (row >= m.n) return;
+    const T *cv = reinterpret_cast<const T *>(m.cval);
+    const T sg = (T)csign;
+    for (int32_t q = m.crowptr[row]; q < m.crowptr[row + 1]; ++q) {
+        const T c = sg * cv[q];
+        const T2 xv = x[m.ccol[q]];
+        ar -= c * xv.y;
+        ai += c * xv.x;
+    }
+    T2 *y = reinterpret_cast<T2 *>(yb + off[s]);
+    if (bb) {
+        const T2 bv = reinterpret_cast<const T2 *>(bb + off[s])[row];
+        y[row] = T2{bv.x - ar, bv.y - ai};
+    } else {
+        y[row] = T2{ar, ai};
+    }
+}
+
+__global__ void __launch_bounds__(256) k_sell_fill(int64_t ne, const int32_t *__restrict__ src,
+                                                   const double *__restrict__ kval, double *__restrict__ v64,
+                                                   float *__restrict__ v32) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= ne) return;
+    const double v = src[e] >= 0 ? kval[src[e]] : 0.0;
+    v64[e] = v;
+    v32[e] = (float)v;
+}
+
+void launch_sell_fill(int64_t ne, const int32_t *src, const double *kval, double *v64, float *v32, hipStream_t st) {
+    if (ne <= 0) return;
+    k_sell_fill<<<(unsigned)((ne + 255) / 256), 256, 0, st>>>(ne, src, kval, v64, v32);
+    THM_HIP(hipGetLastError());
+}
+
+// Variant code v = 10 * lanes_per_row + unroll (unroll 1 or 4), or SPMV_SELL; chosen by
+// the autotuner.
 template <class T>
 void launch_spmv(int v, const MatDesc *mats, const int64_t *off, const Sched &sc, int ns, const int32_t *mask,
                  const T *x, T *y, const T *b, float csign, hipStream_t st) {
@@ -118,6 +199,11 @@ void launch_spmv(int v, const MatDesc *mats, const int64_t *off, const Sched &sc
     const dim3 g(sc.nblocks), blk(256);
 #define SPMV_CASE(L, U) \
     case 10 * L + U: k_spmv<L, U, T><<<g, blk, 0, st>>>(mats, off, sc.blkoff.p, ns, mask, x, y, b, csign); break;
+    if (v == SPMV_SELL) {
+        k_spmv_sell<T><<<g, blk, 0, st>>>(mats, off, sc.blkoff.p, ns, mask, x, y, b, csign);
+        THM_HIP(hipGetLastError());
+        return;
+    }
     switch (v) {
         SPMV_CASE(2, 1) SPMV_CASE(4, 1) SPMV_CASE(8, 1) SPMV_CASE(16, 1) SPMV_CASE(32, 1) SPMV_CASE(64, 1)
         SPMV_CASE(2, 4) SPMV_CASE(4, 4) SPMV_CASE(8, 4) SPMV_CASE(16, 4) SPMV_CASE(32, 4)

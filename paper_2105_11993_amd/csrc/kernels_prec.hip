@@ -504,11 +504,13 @@ __device__ __forceinline__ void load8(const T *p, T (&v)[8]) {
 template <class T, int WPB>
 struct BcrShared {
     T red[WPB / 2][2 * BCR_NM][BCR_RT + 4];  // partial tiles: [wave pair][n][row]
-    // per 8-column chunk kc: position of column 8 kc in a member's vector minus 8 kc,
-    // times 2, plus the source (0 = ws, 1 = ys); chunks past the padded width repeat
-    // the last chunk of the last segment (zero in M)
-    int32_t tab[BCR_TAB];
 };
+
+// Chunk table of the block's task (dynamic LDS, sized per launch by the widest task of the
+// phase, so short phases keep more blocks resident): per 8-column chunk kc, the position
+// of column 8 kc in a member's work vector minus 8 kc, times 2, plus the source (0 = ws,
+// 1 = ys); chunks past the padded width repeat the last chunk of the last segment.
+extern __shared__ int32_t bcr_tab[];
 
 // Operands of one 32-column step: 8 columns of two M rows and of NNT X columns per lane.
 template <class T, int NNT>
@@ -525,7 +527,7 @@ __device__ __forceinline__ void bcr_fetch(BcrStep<T, NNT> &o, const BcrShared<T,
                                           const T *wsb, const T *ysb) {
     load8(A0 + k, o.a0);
     load8(A1 + k, o.a1);
-    const int32_t e = sh.tab[(k >> 3) + ((threadIdx.x >> 4) & 3)];  // this lane group's chunk
+    const int32_t e = bcr_tab[(k >> 3) + ((threadIdx.x >> 4) & 3)];  // this lane group's chunk
     const T *src = (e & 1) ? ysb : wsb;
     const int64_t pos = (int64_t)(e >> 1) + k;
 #pragma unroll
@@ -661,7 +663,7 @@ __global__ void __launch_bounds__(64 * WPB, BcrOcc<T>::v) k_bcr_mfma(const BcrTa
     for (int j = 0; j < 8 * tk.nnt; ++j)
         if (mb + j < m1 && (!mask || mask[memb[mb + j]])) any = true;
     if (!any) return;  // same decision in every thread of the block
-    for (int kc = threadIdx.x; kc < (tk.ld >> 3); kc += blockDim.x) sh.tab[kc] = tk.tab[kc];
+    for (int kc = threadIdx.x; kc < (tk.ld >> 3); kc += blockDim.x) bcr_tab[kc] = tk.tab[kc];
     __syncthreads();
     if (tk.nnt == 1)
         bcr_tile<T, WPB, 1>(tk, sh, rt * BCR_RT, mb, m1, memb, soff, mask, wsb, ysb);
@@ -718,8 +720,8 @@ void launch_bcr_phases(const PrecBatch &P, const int32_t *mask, T *ws, T *ys, hi
     for (const PrecPhase &ph : P.phases) {
         const int nb = ph.sched[prec].nblocks;
         if (!nb) continue;
-        k_bcr_mfma<T, BCR_WPB><<<nb, 64 * BCR_WPB, 0, st>>>(ph.tasks[prec].p, ph.sched[prec].blkoff.p, ph.ntasks,
-                                                          P.memb_ptr.p, P.memb.p, P.soff.p, mask, ws, ys);
+        k_bcr_mfma<T, BCR_WPB><<<nb, 64 * BCR_WPB, sizeof(int32_t) * (ph.max_ld / 8), st>>>(
+            ph.tasks[prec].p, ph.sched[prec].blkoff.p, ph.ntasks, P.memb_ptr.p, P.memb.p, P.soff.p, mask, ws, ys);
     }
     THM_HIP(hipGetLastError());
 }

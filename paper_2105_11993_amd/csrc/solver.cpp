@@ -235,8 +235,10 @@ void Ctx::build(const std::vector<thm_system *> &s, int m, hipStream_t stream) {
     std::vector<const uint8_t *> hd(ns);
     for (int i = 0; i < ns; ++i) {
         const thm_system &S = *sys[i];
-        h64[i] = {S.n, S.k_rowptr.p, S.k_col.p, S.kval.p, S.c_rowptr.p, S.c_col.p, S.cval.p};
-        h32[i] = {S.n, S.k_rowptr.p, S.k_col.p, S.kval32.p, S.c_rowptr.p, S.c_col.p, S.cval32.p};
+        h64[i] = {S.n, S.k_rowptr.p, S.k_col.p, S.kval.p, S.c_rowptr.p, S.c_col.p, S.cval.p,
+                  S.sl_ptr.p, S.sl_col.p, S.sl_val.p};
+        h32[i] = {S.n, S.k_rowptr.p, S.k_col.p, S.kval32.p, S.c_rowptr.p, S.c_col.p, S.cval32.p,
+                  S.sl_ptr.p, S.sl_col.p, S.sl_val32.p};
         hd[i] = S.dir_d.p;
     }
     mat64.upload(h64, st);
@@ -398,6 +400,7 @@ void Ctx::build_prec() {
             std::vector<int32_t> all, one;
             std::vector<int64_t> at;
             for (const BcrTask &t : t64) {
+                ph.max_ld = std::max(ph.max_ld, t.ld);
                 at.push_back((int64_t)all.size());
                 bcr_chunk_table(t, one);
                 all.insert(all.end(), one.begin(), one.end());
@@ -617,7 +620,7 @@ static void tune_store() {
 }
 
 void Ctx::autotune() {
-    const int cand[] = {21, 41, 81, 161, 321, 24, 44, 84, 164, 324};
+    const int cand[] = {21, 41, 81, 161, 321, 24, 44, 84, 164, 324, SPMV_SELL};
     for (int c : cand) K.B.spmv_sched(c, st);
     int64_t nnz = 0, nrows = 0;
     for (thm_system *s : sys) {

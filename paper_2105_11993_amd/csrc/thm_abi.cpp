@@ -254,6 +254,7 @@ static void assemble_K(thm_system &S, hipStream_t st) {
     THM_HIP(hipMemcpyAsync(S.kval.p, S.kraw.p, sizeof(double) * nnz, hipMemcpyDeviceToDevice, st));
     launch_dirichletize(S.n, S.k_rowptr.p, S.k_col.p, S.dir_d.p, S.kval.p, 1, st);
     launch_convert(S.kval.p, S.kval32.p, nnz, st);
+    launch_sell_fill((int64_t)S.sl_src.n, S.sl_src.p, S.kval.p, S.sl_val.p, S.sl_val32.p, st);
 }
 
 static void assemble_system(thm_system &S, const thm_problem &p, uint32_t iface_sides, hipStream_t st) {
@@ -354,6 +355,15 @@ static void assemble_system(thm_system &S, const thm_problem &p, uint32_t iface_
     S.kraw.alloc(nnz);
     S.kval.alloc(nnz);
     S.kval32.alloc(nnz);
+    {
+        std::vector<int32_t> ptr, scol, src;
+        sell_build(S.n, S.K.rowptr, S.K.col, ptr, scol, src);
+        S.sl_ptr.upload(ptr, st);
+        S.sl_col.upload(scol, st);
+        S.sl_src.upload(src, st);
+        S.sl_val.alloc(std::max<size_t>(src.size(), 1));
+        S.sl_val32.alloc(std::max<size_t>(src.size(), 1));
+    }
     assemble_K(S, st);
     // C = k w (M_inf + M_Sigma)
     const int64_t nnzc = (int64_t)S.C.col.size();
@@ -1145,6 +1155,25 @@ thm_status thm_time_spmv(thm_system *sys, int32_t precision, int32_t reps, doubl
         const double nnz = (double)sys->K.col.size() + (double)sys->C.col.size();
         if (bytes_out) *bytes_out = (v + 4.0) * nnz + 2.0 * 4.0 * (sys->n + 1) + 2.0 * 2.0 * sys->n * v;
         stream_join(c.st, us);
+    });
+}
+
+thm_status thm_set_spmv_variant(thm_system *sys, int32_t precision, int32_t variant) {
+    return guard([&] {
+        if (!sys) fail(THM_EINVAL, "bad arguments");
+        if (precision != THM_FP64 && precision != THM_FP32_IR) fail(THM_EINVAL, "unknown precision");
+        static const int known[] = {21, 41, 81, 161, 321, 641, 24, 44, 84, 164, 324, THM_SPMV_SELL};
+        bool ok = variant == -1;
+        for (int k : known) ok = ok || k == variant;
+        if (!ok) fail(THM_EINVAL, "unknown SpMV variant");
+        Ctx &c = get_ctx({sys}, 50);
+        if (variant == -1) {
+            c.autotune();
+            return;
+        }
+        c.K.B.spmv_sched(variant, c.st);
+        if (precision == THM_FP64) c.lpr64 = variant;
+        else c.lpr32 = variant;
     });
 }
 

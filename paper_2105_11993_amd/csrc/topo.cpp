@@ -12,7 +12,7 @@
 #include <algorithm>
 #include <numeric>
 
-#include "thm_internal.h"
+#include "kernels.h"
 
 namespace thm {
 
@@ -394,4 +394,42 @@ void build_layering(const Topo &t, const std::vector<uint8_t> &dir, Layering &L)
     bucket(L.n_skel, key, vall, ptr2, L.cond_loc);
 }
 
+}  // namespace thm
+
+namespace thm {
+// SELL-64 layout of a CSR pattern (see MatDesc): slice s holds rows 64 s .. 64 s + 63,
+// entry (k, lane) of the slice at ptr[s] + 64 k + lane; rows shorter than the slice's
+// longest row (and lanes past the last row) are padded with src = -1 and a valid column.
+void sell_build(int64_t n, const std::vector<int32_t> &rowptr, const std::vector<int32_t> &col,
+                std::vector<int32_t> &ptr, std::vector<int32_t> &scol, std::vector<int32_t> &src) {
+    const int64_t nsl = (n + SELL_C - 1) / SELL_C;
+    ptr.assign(nsl + 1, 0);
+    int64_t tot = 0;
+    for (int64_t s = 0; s < nsl; ++s) {
+        int32_t w = 0;
+        for (int64_t r = s * SELL_C; r < std::min<int64_t>(n, (s + 1) * SELL_C); ++r)
+            w = std::max(w, rowptr[r + 1] - rowptr[r]);
+        tot += (int64_t)w * SELL_C;
+        if (tot > INT32_MAX) fail(THM_EUNSUPPORTED, "matrix too large for 32-bit SELL offsets");
+        ptr[s + 1] = (int32_t)tot;
+    }
+    scol.assign(tot, 0);
+    src.assign(tot, -1);
+    for (int64_t s = 0; s < nsl; ++s) {
+        const int32_t w = (ptr[s + 1] - ptr[s]) / SELL_C;
+        for (int lane = 0; lane < SELL_C; ++lane) {
+            const int64_t r = s * SELL_C + lane;
+            const int32_t len = r < n ? rowptr[r + 1] - rowptr[r] : 0;
+            for (int32_t k = 0; k < w; ++k) {
+                const int64_t e = ptr[s] + (int64_t)k * SELL_C + lane;
+                if (k < len) {
+                    scol[e] = col[rowptr[r] + k];
+                    src[e] = rowptr[r] + k;
+                } else {
+                    scol[e] = r < n ? (int32_t)r : 0;
+                }
+            }
+        }
+    }
+}
 }  // namespace thm

@@ -168,3 +168,60 @@ def test_both_krylov_scalar_modes_match_lu(thm, krylov):
     (E,), (st,) = thm.thm_gmres_solve([S], thm.default_opts(rtol=1e-11, restart=40, krylov=k,
                                                             precision=thm.THM_FP32_IR))
     assert rel(E.cpu().numpy(), Eo) <= 1e-8
+
+
+def test_preconditioner_on_subdomain_shape(thm):
+    """A 64x64, degree-2 square (the shape of one C2 subdomain: 65 layers of 387 skeleton
+    DoFs, three cyclic-reduction levels and a dense last system of 9 blocks): the MFMA
+    apply inverts K exactly in FP64, to FP32 accuracy in FP32, and is bitwise
+    reproducible."""
+    import torch
+    d = _randomize(spec(2, 64, 2, 50.0), 40)
+    print("case subdomain shape d2m64p2", flush=True)
+    S = thm.thm_assemble(d)
+    so = system.assemble(problem(d))
+    Sd, _ = dirichletized(so)
+    K = Sd.real
+    rng = np.random.default_rng(41)
+    x = rng.standard_normal(S.n) + 1j * rng.standard_normal(S.n)
+    xt = torch.from_numpy(x).cuda()
+    z = thm.thm_apply_precond(S, xt).cpu().numpy()
+    knorm = abs(K).sum(axis=1).max()
+    eta = np.linalg.norm(K @ z - x, np.inf) / (knorm * np.linalg.norm(z, np.inf) + np.linalg.norm(x, np.inf))
+    assert eta <= 1e-11
+    z2 = thm.thm_apply_precond(S, xt).cpu().numpy()
+    assert np.array_equal(z, z2)
+    z32 = thm.thm_apply_precond(S, xt, precision=thm.THM_FP32_IR).cpu().numpy()
+    eta32 = np.linalg.norm(K @ z32 - x, np.inf) / (knorm * np.linalg.norm(z32, np.inf) + np.linalg.norm(x, np.inf))
+    # FP32 unit roundoff (6e-8) times a growth of at most ~1600 from the explicit block
+    # inverses (measured ~175 here); a wrong or missing partial tile gives an O(1) error
+    assert eta32 <= 1e-4
+
+
+@pytest.mark.parametrize("d", [spec(2, 11, 2, 9.0), spec(3, 5, 1, 6.0)], ids=lambda c: f"d{c['dim']}m{c['n'][0]}p{c['p']}")
+def test_every_spmv_variant_matches_oracle(thm, d):
+    """Each SpMV variant the autotuner can pick (CSR-vector lanes/unroll and SELL-64) gives
+    the oracle's operator [[K, -C], [C, K]] (and its transpose) on the same input, with a
+    ragged last slice (n not a multiple of 64)."""
+    import torch
+    d = _randomize(d, 50)
+    print("case spmv variants", _ids(d), flush=True)
+    S = thm.thm_assemble(d)
+    so = system.assemble(problem(d))
+    Sd, _ = dirichletized(so)
+    assert S.n % 64 != 0
+    rng = np.random.default_rng(51)
+    x = rng.standard_normal(S.n) + 1j * rng.standard_normal(S.n)
+    xt = torch.from_numpy(x).cuda()
+    for v in thm.SPMV_VARIANTS:
+        for prec in (thm.THM_FP64, thm.THM_FP32_IR):
+            thm.thm_set_spmv_variant(S, prec, v)
+        for tr in (False, True):
+            ref = (Sd.conj() if tr else Sd) @ x
+            y = thm.thm_apply_operator(S, xt, transpose=tr).cpu().numpy()
+            assert rel(y, ref) <= 1e-14, (v, tr)
+            y32 = thm.thm_apply_operator(S, xt, transpose=tr, precision=thm.THM_FP32_IR).cpu().numpy()
+            assert rel(y32, ref) <= 1e-6, (v, tr)
+    thm.thm_set_spmv_variant(S, thm.THM_FP64, -1)
+    with pytest.raises(thm.ThmError):
+        thm.thm_set_spmv_variant(S, thm.THM_FP64, 17)
