@@ -15,16 +15,20 @@ struct MatDesc {
     const void *kval;
     const int32_t *crowptr, *ccol;
     const void *cval;
-    // K in SELL-64 (slices of 64 consecutive rows, entries column-major within a slice,
-    // padded to the longest row of the slice with zero values): the same values as kval
+    // K in SELL-64 (rows sorted by length within windows of SELL_SIGMA, slices of 64,
+    // entries column-major within a slice, padded to the slice's longest row with zero
+    // values): the same values as kval
     const int32_t *sl_ptr, *sl_col;  // entry offset of each slice (n_slices + 1); columns
+    const int32_t *sl_row;           // original row of each slice lane (-1: none)
     const void *sl_val;
 };
 constexpr int SELL_C = 64;        // rows per slice (one wave, one row per lane)
+constexpr int SELL_SIGMA = 1024;  // sorting window (rows)
 constexpr int SPMV_SELL = 19;     // SpMV variant code of the SELL-64 kernel (256 rows per block)
 // Host: SELL-64 layout of a CSR pattern; src[e] = CSR index of entry e, or -1 (padding).
 void sell_build(int64_t n, const std::vector<int32_t> &rowptr, const std::vector<int32_t> &col,
-                std::vector<int32_t> &ptr, std::vector<int32_t> &scol, std::vector<int32_t> &src);
+                std::vector<int32_t> &ptr, std::vector<int32_t> &scol, std::vector<int32_t> &src,
+                std::vector<int32_t> &row);
 // Device: SELL values from the CSR values (FP64 and FP32 copies).
 void launch_sell_fill(int64_t ne, const int32_t *src, const double *kval, double *v64, float *v32, hipStream_t st);
 

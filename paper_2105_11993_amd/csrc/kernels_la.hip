@@ -110,7 +110,7 @@ __global__ void __launch_bounds__(256) k_spmv(const MatDesc *__restrict__ mats, 
     }
 }
 
-// SELL-64 variant: one wave per slice of 64 rows, one row per lane.  The value and
+// SELL-64 variant: one wave per slice of 64 (length-sorted) rows, one row per lane.  The value and
 // column loads of a wave are 64 consecutive entries (coalesced), there is no cross-lane
 // reduction and no divergence inside the K loop; padding entries have value 0 and point
 // at a valid column.  The boundary operator C (few rows) is applied from its CSR.
@@ -126,7 +126,7 @@ __global__ void __launch_bounds__(256) k_spmv_sell(const MatDesc *__restrict__ m
     const int64_t slice = (int64_t)(blockIdx.x - blkoff[s]) * 4 + (threadIdx.x >> 6);
     if (slice * SELL_C >= m.n) return;  // whole wave
     const int lane = threadIdx.x & 63;
-    const int64_t row = slice * SELL_C + lane;
+    const int32_t row = m.sl_row[slice * SELL_C + lane];
     const T2 *x = reinterpret_cast<const T2 *>(xb + off[s]);
     const int32_t e0 = m.sl_ptr[slice], w = (m.sl_ptr[slice + 1] - e0) / SELL_C;
     const int32_t *cp = m.sl_col + e0 + lane;
@@ -156,7 +156,7 @@ __global__ void __launch_bounds__(256) k_spmv_sell(const MatDesc *__restrict__ m
         ar += v * xv.x;
         ai += v * xv.y;
     }
-    if (row >= m.n) return;
+    if (row < 0) return;
     const T *cv = reinterpret_cast<const T *>(m.cval);
     const T sg = (T)csign;
     for (int32_t q = m.crowptr[row]; q < m.crowptr[row + 1]; ++q) {

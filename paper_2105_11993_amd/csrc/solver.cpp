@@ -236,9 +236,9 @@ void Ctx::build(const std::vector<thm_system *> &s, int m, hipStream_t stream) {
     for (int i = 0; i < ns; ++i) {
         const thm_system &S = *sys[i];
         h64[i] = {S.n, S.k_rowptr.p, S.k_col.p, S.kval.p, S.c_rowptr.p, S.c_col.p, S.cval.p,
-                  S.sl_ptr.p, S.sl_col.p, S.sl_val.p};
+                  S.sl_ptr.p, S.sl_col.p, S.sl_row.p, S.sl_val.p};
         h32[i] = {S.n, S.k_rowptr.p, S.k_col.p, S.kval32.p, S.c_rowptr.p, S.c_col.p, S.cval32.p,
-                  S.sl_ptr.p, S.sl_col.p, S.sl_val32.p};
+                  S.sl_ptr.p, S.sl_col.p, S.sl_row.p, S.sl_val32.p};
         hd[i] = S.dir_d.p;
     }
     mat64.upload(h64, st);

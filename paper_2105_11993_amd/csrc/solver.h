@@ -71,7 +71,7 @@ struct thm_system {
     thm::DBuf<double> mu_d;
     thm::DBuf<double> kel, kraw, kval, craw, cval;
     thm::DBuf<float> kval32, cval32;
-    thm::DBuf<int32_t> sl_ptr, sl_col, sl_src;  // K in SELL-64 (see MatDesc)
+    thm::DBuf<int32_t> sl_ptr, sl_col, sl_src, sl_row;  // K in SELL-64 (see MatDesc)
     thm::DBuf<double> sl_val;
     thm::DBuf<float> sl_val32;
     thm::DBuf<uint8_t> dir_d;

@@ -356,8 +356,9 @@ static void assemble_system(thm_system &S, const thm_problem &p, uint32_t iface_
     S.kval.alloc(nnz);
     S.kval32.alloc(nnz);
     {
-        std::vector<int32_t> ptr, scol, src;
-        sell_build(S.n, S.K.rowptr, S.K.col, ptr, scol, src);
+        std::vector<int32_t> ptr, scol, src, row;
+        sell_build(S.n, S.K.rowptr, S.K.col, ptr, scol, src, row);
+        S.sl_row.upload(row, st);
         S.sl_ptr.upload(ptr, st);
         S.sl_col.upload(scol, st);
         S.sl_src.upload(src, st);

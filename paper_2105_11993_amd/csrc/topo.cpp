@@ -397,18 +397,31 @@ void build_layering(const Topo &t, const std::vector<uint8_t> &dir, Layering &L)
 }  // namespace thm
 
 namespace thm {
-// SELL-64 layout of a CSR pattern (see MatDesc): slice s holds rows 64 s .. 64 s + 63,
-// entry (k, lane) of the slice at ptr[s] + 64 k + lane; rows shorter than the slice's
-// longest row (and lanes past the last row) are padded with src = -1 and a valid column.
+// SELL-64 layout of a CSR pattern (see MatDesc).  Rows are sorted by decreasing length
+// inside windows of SELL_SIGMA consecutive rows (stable, so equal lengths keep their
+// order), then cut into slices of 64; row[s * 64 + lane] is the original row of a lane
+// (-1 past the last row).  Entry (k, lane) of slice s sits at ptr[s] + 64 k + lane; rows
+// shorter than the slice's longest row are padded with src = -1 and a valid column.
 void sell_build(int64_t n, const std::vector<int32_t> &rowptr, const std::vector<int32_t> &col,
-                std::vector<int32_t> &ptr, std::vector<int32_t> &scol, std::vector<int32_t> &src) {
+                std::vector<int32_t> &ptr, std::vector<int32_t> &scol, std::vector<int32_t> &src,
+                std::vector<int32_t> &row) {
     const int64_t nsl = (n + SELL_C - 1) / SELL_C;
+    row.assign(nsl * SELL_C, -1);
+    for (int64_t w0 = 0; w0 < n; w0 += SELL_SIGMA) {
+        const int64_t w1 = std::min<int64_t>(n, w0 + SELL_SIGMA);
+        std::vector<int32_t> ord(w1 - w0);
+        std::iota(ord.begin(), ord.end(), (int32_t)w0);
+        std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) {
+            return rowptr[a + 1] - rowptr[a] > rowptr[b + 1] - rowptr[b];
+        });
+        std::copy(ord.begin(), ord.end(), row.begin() + w0);
+    }
+    auto len = [&](int64_t slot) { return row[slot] < 0 ? 0 : rowptr[row[slot] + 1] - rowptr[row[slot]]; };
     ptr.assign(nsl + 1, 0);
     int64_t tot = 0;
     for (int64_t s = 0; s < nsl; ++s) {
         int32_t w = 0;
-        for (int64_t r = s * SELL_C; r < std::min<int64_t>(n, (s + 1) * SELL_C); ++r)
-            w = std::max(w, rowptr[r + 1] - rowptr[r]);
+        for (int lane = 0; lane < SELL_C; ++lane) w = std::max(w, len(s * SELL_C + lane));
         tot += (int64_t)w * SELL_C;
         if (tot > INT32_MAX) fail(THM_EUNSUPPORTED, "matrix too large for 32-bit SELL offsets");
         ptr[s + 1] = (int32_t)tot;
@@ -418,15 +431,15 @@ void sell_build(int64_t n, const std::vector<int32_t> &rowptr, const std::vector
     for (int64_t s = 0; s < nsl; ++s) {
         const int32_t w = (ptr[s + 1] - ptr[s]) / SELL_C;
         for (int lane = 0; lane < SELL_C; ++lane) {
-            const int64_t r = s * SELL_C + lane;
-            const int32_t len = r < n ? rowptr[r + 1] - rowptr[r] : 0;
+            const int32_t r = row[s * SELL_C + lane];
+            const int32_t l = len(s * SELL_C + lane);
             for (int32_t k = 0; k < w; ++k) {
                 const int64_t e = ptr[s] + (int64_t)k * SELL_C + lane;
-                if (k < len) {
+                if (k < l) {
                     scol[e] = col[rowptr[r] + k];
                     src[e] = rowptr[r] + k;
                 } else {
-                    scol[e] = r < n ? (int32_t)r : 0;
+                    scol[e] = r >= 0 ? r : 0;
                 }
             }
         }
