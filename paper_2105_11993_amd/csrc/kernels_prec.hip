@@ -504,6 +504,7 @@ __device__ __forceinline__ void load8(const T *p, T (&v)[8]) {
 template <class T, int WPB>
 struct BcrShared {
     T red[WPB / 2][2 * BCR_NM][BCR_RT + 4];  // partial tiles: [wave pair][n][row]
+    T yold[BCR_RT * 2 * BCR_NM];             // outputs read back by subtracting tasks
 };
 
 // Chunk table of the block's task (dynamic LDS, sized per launch by the widest task of the
@@ -521,17 +522,23 @@ struct BcrStep {
 // Loads of one step; branch-free so that the next step's loads stay in flight while
 // the current step's MFMAs run.  Lanes of absent members read the chunk's first
 // member (their output columns are never stored).
+template <class T, int NNT>
+__device__ __forceinline__ void bcr_fetch_b(BcrStep<T, NNT> &o, const int64_t (&bbase)[NNT], int k, const T *wsb,
+                                            const T *ysb) {
+    const int32_t e = bcr_tab[(k >> 3) + ((threadIdx.x >> 4) & 3)];  // this lane group's chunk
+    const T *src = (e & 1) ? ysb : wsb;
+    const int64_t pos = (int64_t)(e >> 1) + k;
+#pragma unroll
+    for (int nt = 0; nt < NNT; ++nt) load8(src + bbase[nt] + pos, o.b[nt]);
+}
+
 template <class T, int WPB, int NNT>
 __device__ __forceinline__ void bcr_fetch(BcrStep<T, NNT> &o, const BcrShared<T, WPB> &sh,
                                           const int64_t (&bbase)[NNT], const T *A0, const T *A1, int k,
                                           const T *wsb, const T *ysb) {
     load8(A0 + k, o.a0);
     load8(A1 + k, o.a1);
-    const int32_t e = bcr_tab[(k >> 3) + ((threadIdx.x >> 4) & 3)];  // this lane group's chunk
-    const T *src = (e & 1) ? ysb : wsb;
-    const int64_t pos = (int64_t)(e >> 1) + k;
-#pragma unroll
-    for (int nt = 0; nt < NNT; ++nt) load8(src + bbase[nt] + pos, o.b[nt]);
+    bcr_fetch_b(o, bbase, k, wsb, ysb);
 }
 
 template <class T, int NNT>
@@ -571,12 +578,33 @@ __device__ __forceinline__ void bcr_tile(const BcrTask &tk, BcrShared<T, WPB> &s
         for (int nt = 0; nt < NNT; ++nt) acc[mt][nt] = V4{0, 0, 0, 0};
     const int kbeg = wave * tk.kq;
     const int nst = max(0, (min(tk.ld, kbeg + tk.kq) - kbeg) / BCR_KS);  // same for the whole wave
+    // Latency of the block start: the first step's M operands and the outputs that a
+    // subtracting task reads back are requested before the chunk table is copied (the
+    // X operands need the table).
+    BcrStep<T, NNT> p, q;
+    if (nst > 0) {
+        load8(A0 + kbeg, p.a0);
+        load8(A1 + kbeg, p.a1);
+    }
+    constexpr int NOUT = BCR_RT * 16 * NNT;
+    constexpr int NPT = (NOUT + 64 * WPB - 1) / (64 * WPB);  // outputs per thread
+    if (tk.subtract) {
+#pragma unroll
+        for (int i = 0; i < NPT; ++i) {
+            const int o = threadIdx.x + i * 64 * WPB;
+            const int n = o / BCR_RT, r = o % BCR_RT;
+            const int mi = mb + (n >> 1);
+            if (o < NOUT && row0 + r < tk.rows && mi < m1)
+                sh.yold[o] = ((tk.out_dst ? ysb : wsb) + soff[memb[mi]] + (n & 1) * tk.sp + tk.out_off)[row0 + r];
+        }
+    }
+    for (int kc = threadIdx.x; kc < (tk.ld >> 3); kc += blockDim.x) bcr_tab[kc] = tk.tab[kc];
+    __syncthreads();
     if (nst > 0) {
         // two operand buffers in turn; the prefetch past the last step repeats the last
         // step's addresses
-        BcrStep<T, NNT> p, q;
         const int klast = kbeg + (nst - 1) * BCR_KS;
-        bcr_fetch<T, WPB, NNT>(p, sh, bbase, A0, A1, kbeg, wsb, ysb);
+        bcr_fetch_b(p, bbase, kbeg, wsb, ysb);
         // (the scheduling barriers keep the prefetch ahead of the MFMAs it overlaps)
         for (int st = 0;; st += 2) {
             bcr_fetch<T, WPB, NNT>(q, sh, bbase, A0, A1, min(kbeg + (st + 1) * BCR_KS, klast), wsb, ysb);
@@ -616,21 +644,19 @@ __device__ __forceinline__ void bcr_tile(const BcrTask &tk, BcrShared<T, WPB> &s
                 }
     }
     __syncthreads();
-    constexpr int NOUT = BCR_RT * 16 * NNT;
-    for (int o = threadIdx.x; o < NOUT; o += 64 * WPB) {
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+        const int o = threadIdx.x + i * 64 * WPB;
         const int n = o / BCR_RT, r = o % BCR_RT;
         const int mi = mb + (n >> 1);
-        if (row0 + r >= tk.rows || mi >= m1) continue;
+        if (o >= NOUT || row0 + r >= tk.rows || mi >= m1) continue;
         const int s = memb[mi];
         if (mask && !mask[s]) continue;
         T v = 0;
 #pragma unroll
         for (int w = 0; w < H; ++w) v += sh.red[w][n][r];
         T *y = (tk.out_dst ? ysb : wsb) + soff[s] + (n & 1) * tk.sp + tk.out_off + row0 + r;
-        if (tk.subtract)
-            *y -= v;
-        else
-            *y = v;
+        *y = tk.subtract ? sh.yold[o] - v : v;
     }
 }
 
@@ -659,12 +685,10 @@ __global__ void __launch_bounds__(64 * WPB, BcrOcc<T>::v) k_bcr_mfma(const BcrTa
     const int rt = local / tk.nmc, mchunk = local - rt * tk.nmc;
     const int m1 = memb_ptr[tk.group + 1];
     const int mb = memb_ptr[tk.group] + mchunk * 8 * tk.nnt;
-    bool any = false;
-    for (int j = 0; j < 8 * tk.nnt; ++j)
-        if (mb + j < m1 && (!mask || mask[memb[mb + j]])) any = true;
-    if (!any) return;  // same decision in every thread of the block
-    for (int kc = threadIdx.x; kc < (tk.ld >> 3); kc += blockDim.x) bcr_tab[kc] = tk.tab[kc];
-    __syncthreads();
+    // any active member in this chunk: one flag per lane, the same ballot in every wave
+    const int lane = threadIdx.x & 63;
+    const bool on = lane < 8 * tk.nnt && mb + lane < m1 && (!mask || mask[memb[mb + lane]]);
+    if (!__ballot(on)) return;  // same decision in every thread of the block
     if (tk.nnt == 1)
         bcr_tile<T, WPB, 1>(tk, sh, rt * BCR_RT, mb, m1, memb, soff, mask, wsb, ysb);
     else
