@@ -99,6 +99,9 @@ typedef struct {
     double rel_residual;     /* final FP64 relative residual of the (glued) solution */
     double setup_ms;         /* preconditioner factorisation time inside this call */
     double solve_ms;         /* solve time inside this call */
+    int32_t fp64_fallback;   /* THM_FP32_IR: solves finished by FP64 GMRES because a refinement step did not
+                                halve the FP64 residual or max_refine was reached (DDM: summed over the
+                                subdomain solves); 0 otherwise */
 } thm_stats;
 
 typedef struct {

@@ -493,6 +493,7 @@ KOps<float> Ctx::ops32(float csign, bool with_prec) {
 void Ctx::solve(const thm_solve_opts &o, float csign, const int32_t *mask, std::vector<int> &iters,
                 std::vector<int> &refines, std::vector<double> &resid) {
     if (!mask) mask = mask_all.p;
+    last_fb.assign(ns, 0);
     iters.assign(ns, 0);
     refines.assign(ns, 0);
     resid.assign(ns, 0.0);
@@ -523,25 +524,64 @@ void Ctx::solve(const thm_solve_opts &o, float csign, const int32_t *mask, std::
     THM_HIP(hipMemcpyAsync(run_ir.p, mask, sizeof(int32_t) * ns, hipMemcpyDeviceToDevice, st));
     // FP32 inner solves: one GMRES cycle each (stopped by the FP64 Givens estimate);
     // accuracy comes from the FP64 refinement loop, not from the FP32 residual.
+    // Safeguard: a step that does not at least halve a system's FP64 residual (the FP32
+    // factor is too inaccurate for that system's K, e.g. near a resonance) is undone and
+    // the system is finished by FP64 GMRES from its current iterate, as is every system
+    // still running when max_refine steps are spent.
     GmresParams ip = gp;
     ip.rtol = o.ir_inner_rtol;
     ip.max_iter = std::min(o.max_iter, K.m);
+    std::vector<double> prev(ns, HUGE_VAL), rn_last(ns, 0.0), hrn(ns);
+    std::vector<int32_t> stepped(ns, 0), fb(ns, 0), undo(ns, 0);
+    auto upload_flags = [&](DBuf<int32_t> &dst, const std::vector<int32_t> &h) {
+        THM_HIP(hipMemcpyAsync(dst.p, h.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, st));
+    };
+    if (!ir_aux.n) ir_aux.alloc(ns);
+    if (!ir_scal.n) ir_scal.alloc(ns);
     for (int it = 0;; ++it) {
         A64.apply(x64.p, r64.p, b64.p, run_ir.p);
         launch_norm2<double>(K.B, run_ir.p, r64.p, K.part.p, st);
         launch_norm_finish(K.B, K.part.p, run_ir.p, rnorm.p, bnorm64.p, o.rtol, resid64.p, run_ir.p, st);
         THM_HIP(hipMemcpyAsync(hi.data(), run_ir.p, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, st));
+        THM_HIP(hipMemcpyAsync(hr.data(), resid64.p, sizeof(double) * ns, hipMemcpyDeviceToHost, st));
+        THM_HIP(hipMemcpyAsync(hrn.data(), rnorm.p, sizeof(double) * ns, hipMemcpyDeviceToHost, st));
         THM_HIP(hipStreamSynchronize(st));
+        bool any_undo = false;
+        for (int i = 0; i < ns; ++i) {
+            undo[i] = stepped[i] && !(hr[i] <= 0.5 * prev[i]) && hr[i] > o.rtol;
+            if (undo[i]) {
+                any_undo = true;
+                fb[i] = 1;
+                hi[i] = 0;
+                hr[i] = prev[i];
+            }
+            stepped[i] = 0;
+        }
+        if (any_undo) {
+            // x -= (previous residual norm) * (previous FP32 correction), still in x32
+            std::vector<double> neg(ns);
+            for (int i = 0; i < ns; ++i) neg[i] = -rn_last[i];
+            THM_HIP(hipMemcpyAsync(ir_scal.p, neg.data(), sizeof(double) * ns, hipMemcpyHostToDevice, st));
+            upload_flags(ir_aux, undo);
+            launch_axpy<double, float>(K.B, ir_aux.p, ir_scal.p, x32.p, x64.p, st);
+            upload_flags(run_ir, hi);
+        }
         bool any = false;
         for (int i = 0; i < ns; ++i) any = any || hi[i];
-        if (!any || it >= o.max_refine) break;
+        if (!any) break;
+        if (it >= o.max_refine) {
+            for (int i = 0; i < ns; ++i)
+                if (hi[i]) fb[i] = 1;
+            break;
+        }
         double worst = 0.0;
-        THM_HIP(hipMemcpyAsync(hr.data(), resid64.p, sizeof(double) * ns, hipMemcpyDeviceToHost, st));
-        THM_HIP(hipStreamSynchronize(st));
         for (int i = 0; i < ns; ++i)
             if (hi[i]) {
                 refines[i]++;
                 worst = std::max(worst, hr[i]);
+                prev[i] = hr[i];
+                rn_last[i] = hrn[i];
+                stepped[i] = 1;
             }
         // the inner FP32 solve only has to gain the remaining factor (with margin),
         // but never goes below what FP32 Arnoldi resolves
@@ -557,6 +597,22 @@ void Ctx::solve(const thm_solve_opts &o, float csign, const int32_t *mask, std::
     THM_HIP(hipMemcpyAsync(hr.data(), resid64.p, sizeof(double) * ns, hipMemcpyDeviceToHost, st));
     THM_HIP(hipStreamSynchronize(st));
     for (int i = 0; i < ns; ++i) resid[i] = hr[i];
+    bool any_fb = false;
+    for (int i = 0; i < ns; ++i) any_fb = any_fb || fb[i];
+    if (any_fb) {
+        upload_flags(ir_aux, fb);
+        gmres_run<double>(K, A64, b64.p, x64.p, ir_aux.p, gp, st);
+        THM_HIP(hipMemcpyAsync(hi.data(), K.iters.p, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, st));
+        THM_HIP(hipMemcpyAsync(hr.data(), K.resid.p, sizeof(double) * ns, hipMemcpyDeviceToHost, st));
+        THM_HIP(hipStreamSynchronize(st));
+        for (int i = 0; i < ns; ++i)
+            if (fb[i]) {
+                iters[i] += hi[i];
+                resid[i] = hr[i];
+                fp64_fallbacks++;
+                last_fb[i] = 1;
+            }
+    }
 }
 
 double Ctx::time_bcr(int prec, int reps, double *bytes, int *launches) {

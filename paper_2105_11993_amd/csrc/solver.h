@@ -155,7 +155,10 @@ struct Ctx {
     DBuf<const uint8_t *> dirs;
     DBuf<double> x64, b64, r64, ws64, ys64, tw64;
     DBuf<float> x32, b32, ws32, ys32, tw32;
-    DBuf<int32_t> mask_all, run_ir;
+    DBuf<int32_t> mask_all, run_ir, ir_aux;
+    DBuf<double> ir_scal;
+    int64_t fp64_fallbacks = 0;  // systems finished in FP64 after a failed refinement step (cumulative)
+    std::vector<int32_t> last_fb;  // per system, last solve: finished in FP64
     DBuf<double> rnorm, bnorm64, resid64;
     int lpr64 = 81, lpr32 = 81;  // SpMV variants (10 * lanes_per_row + unroll)
 

@@ -618,6 +618,7 @@ struct DdmRun {
     bool batched;
     hipStream_t st;
     int sweeps_inner_iters = 0;
+    int fallbacks = 0;  // subdomain solves finished in FP64 (THM_FP32_IR)
 
     // E_s for all subdomains given interface data Gv (nullable = 0) and the incident flag.
     void inner_solve(const double *Gv, bool incident) {
@@ -639,6 +640,7 @@ struct DdmRun {
             THM_HIP(hipMemsetAsync(c.x64.p, 0, sizeof(double) * c.x64.n, c.st));
             c.solve(inner_o, 1.f, nullptr, it, rf, rs);
             for (int v : it) maxit = std::max(maxit, v);
+            for (int f : c.last_fb) fallbacks += f;
             if (incident)
                 for (int s = 0; s < ns; ++s)
                     launch_expand_dirichlet(G.subs[s]->n, G.subs[s]->dir_d.p, G.subs[s]->gD.p,
@@ -662,6 +664,7 @@ struct DdmRun {
                 THM_HIP(hipMemsetAsync(c.x64.p, 0, sizeof(double) * c.x64.n, c.st));
                 c.solve(inner_o, 1.f, nullptr, it, rf, rs);
                 maxit = std::max(maxit, it[0]);
+                fallbacks += c.last_fb[0];
                 if (incident)
                     launch_expand_dirichlet(G.subs[s]->n, G.subs[s]->dir_d.p, G.subs[s]->gD.p, c.x64.p, c.st);
                 THM_HIP(hipStreamSynchronize(c.st));
@@ -830,6 +833,7 @@ static void ddm_solve_impl(thm_system &G, const thm_solve_opts &o, double *E, th
     stt.iters = run.sweeps_inner_iters;
     stt.outer_iters = outer;
     stt.refinements = 0;
+    stt.fp64_fallback = run.fallbacks;
     stt.rel_residual = res;
     stt.setup_ms = setup + (t1 - t0);
     stt.solve_ms = now_ms() - t1;
@@ -929,6 +933,7 @@ thm_status thm_gmres_solve(int32_t nsys, thm_system *const *sys, const thm_solve
                 o.iters = it[s];
                 o.outer_iters = 0;
                 o.refinements = rf[s];
+                o.fp64_fallback = c.last_fb[s];
                 o.rel_residual = rs[s];
                 o.status = (rs[s] <= opts->rtol) ? THM_OK : THM_NOT_CONVERGED;
                 o.setup_ms = (grp[s]->fac ? grp[s]->fac->setup_ms : 0.0) + (t1 - t0);

@@ -97,3 +97,31 @@ def test_c2_full_size_sampled(thm):
     Eh = E.cpu().numpy()
     assert system.relative_residual(so, Eh) <= 1.5e-8
     assert rel(Eh[so.D], so.gD) <= 1e-13
+
+
+def test_refinement_fallback_is_fp64_accurate(thm):
+    """With no refinement steps allowed, every system is finished by FP64 GMRES from its
+    iterate: FP64 accuracy, and the stats report the fallback."""
+    from tests._gpu_helpers import spec
+    d = spec(2, 12, 2, 12.0)
+    print("case forced fp64 finish", flush=True)
+    S = thm.thm_assemble(d)
+    Eo = system.solve_lu(system.assemble(problem(d)))
+    (E,), (st,) = thm.thm_gmres_solve([S], thm.default_opts(rtol=1e-13, restart=40, precision=thm.THM_FP32_IR,
+                                                            max_refine=0))
+    assert st["status"] == 0 and st["fp64_fallback"] == 1
+    assert rel(E.cpu().numpy(), Eo) <= 1e-10
+
+
+def test_c4_half_size_batch_reaches_tolerance_in_fp32_refinement(thm):
+    """All 256 problems of the uneven batch (meshes halved) reach 1e-8 in the FP32 +
+    refinement form; problems whose FP32 factor is too inaccurate (high w, near-resonant
+    K) are detected by the refinement safeguard and finished in FP64."""
+    specs = workloads.c4(256, scale=2)
+    print("case c4 half size fp32", flush=True)
+    systems = [thm.thm_assemble(d) for d in specs]
+    Es, sts = thm.thm_gmres_solve(systems, thm.default_opts(rtol=1e-8, restart=64, precision=thm.THM_FP32_IR),
+                                  allow_not_converged=True)
+    bad = [(i, s["rel_residual"]) for i, s in enumerate(sts) if not (s["status"] == 0 and s["rel_residual"] <= 1e-8)]
+    print("fp64 fallbacks:", sum(s["fp64_fallback"] for s in sts), flush=True)
+    assert not bad, bad[:5]
