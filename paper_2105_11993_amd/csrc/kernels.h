@@ -141,7 +141,10 @@ struct PrecDesc {
     const int32_t *dof_pos;    // global DoF -> padded position (-1: interior)
     const int32_t *cell_pos;   // n_cells * ne: padded positions of each cell's skeleton DoFs
     const int32_t *cond_ptr, *cond_cell, *cond_loc;
-    const void *kiinv, *F;         // double or float
+    // double or float: per cell K_ii^{-1} stored transposed ([c][q][m] = (K_ii^{-1})_{mq}),
+    // F_c = K'_ei K_ii^{-1} ([c][le][m]) and its transpose ([c][m][le]); the transposed
+    // layouts make the reads of one cell's threads consecutive
+    const void *kiinv, *F, *FT;
 };
 
 // One dense task of the cyclic-reduction application (see kernels_prec.hip): the
@@ -182,6 +185,8 @@ struct RepackDesc {
     int32_t seg_col[SEGMAX], seg_len[SEGMAX], seg_pstart[SEGMAX];
 };
 void launch_repack(const std::vector<RepackDesc> &d, double *dst64, float *dst32, hipStream_t st);
+// dst[b] = src[b]^T for count row-major rows x cols matrices (setup only)
+void launch_batch_transpose(int64_t count, int rows, int cols, const double *src, double *dst, hipStream_t st);
 
 struct PrecPhase {
     DBuf<BcrTask> tasks[2];    // FP64, FP32 matrices

@@ -411,12 +411,13 @@ __global__ void __launch_bounds__(256) k_cond_fr(const PrecDesc *__restrict__ pd
     const int64_t e = (int64_t)(blockIdx.x - blkoff[s]) * 256 + threadIdx.x;
     if (e >= (int64_t)d.n_cells * d.ne) return;
     const int64_t c = e / d.ne;
-    const T *f = reinterpret_cast<const T *>(d.F) + e * d.n_int;
+    const int le = (int)(e - c * d.ne);
+    const T *f = reinterpret_cast<const T *>(d.FT) + c * d.n_int * d.ne + le;  // F^T[c][m][le]
     const T2 *ri = reinterpret_cast<const T2 *>(rb + off[s]) + d.cell_off + c * d.n_int;
     T2 acc{0, 0};
 #pragma unroll 4
     for (int m = 0; m < d.n_int; ++m) {
-        const T fv = f[m];
+        const T fv = f[(int64_t)m * d.ne];
         const T2 rv = ri[m];
         acc.x += fv * rv.x;
         acc.y += fv * rv.y;
@@ -718,13 +719,13 @@ __global__ void __launch_bounds__(256) k_cond_bwd(const PrecDesc *__restrict__ p
     const int gi = (int)(g - d.cell_off);
     const int64_t c = gi / d.n_int;
     const int m = gi - (int)c * d.n_int;
-    const T *Ki = reinterpret_cast<const T *>(d.kiinv) + (c * d.n_int + m) * d.n_int;
+    const T *Ki = reinterpret_cast<const T *>(d.kiinv) + c * d.n_int * d.n_int + m;  // transposed: [c][q][m]
     const T2 *ri = r + d.cell_off + c * d.n_int;
     T2 acc{0, 0};
 #pragma unroll 4
     for (int q = 0; q < d.n_int; ++q) {
-        acc.x += Ki[q] * ri[q].x;
-        acc.y += Ki[q] * ri[q].y;
+        acc.x += Ki[q * d.n_int] * ri[q].x;
+        acc.y += Ki[q * d.n_int] * ri[q].y;
     }
     const T *F = reinterpret_cast<const T *>(d.F) + c * d.ne * d.n_int;
     const int32_t *cp = d.cell_pos + c * d.ne;
@@ -751,6 +752,23 @@ void launch_bcr_phases(const PrecBatch &P, const int32_t *mask, T *ws, T *ys, hi
 }
 template void launch_bcr_phases<double>(const PrecBatch &, const int32_t *, double *, double *, hipStream_t);
 template void launch_bcr_phases<float>(const PrecBatch &, const int32_t *, float *, float *, hipStream_t);
+
+// ------------------------------------------------------------------ batched transpose (setup)
+__global__ void __launch_bounds__(256) k_batch_transpose(int64_t total, int rows, int cols,
+                                                         const double *__restrict__ src, double *__restrict__ dst) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= total) return;
+    const int64_t per = (int64_t)rows * cols, b = e / per;
+    const int rem = (int)(e - b * per), i = rem / cols, j = rem - i * cols;
+    dst[b * per + (int64_t)j * rows + i] = src[e];
+}
+
+void launch_batch_transpose(int64_t count, int rows, int cols, const double *src, double *dst, hipStream_t st) {
+    const int64_t total = count * rows * cols;
+    if (total <= 0) return;
+    k_batch_transpose<<<(unsigned)((total + 255) / 256), 256, 0, st>>>(total, rows, cols, src, dst);
+    THM_HIP(hipGetLastError());
+}
 
 // ------------------------------------------------------------------ padded copies (setup)
 __global__ void __launch_bounds__(256) k_repack(const RepackDesc *__restrict__ ds, const int32_t *__restrict__ blkoff,

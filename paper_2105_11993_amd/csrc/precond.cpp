@@ -425,10 +425,21 @@ void setup_precond(const std::vector<thm_system *> &all, hipStream_t st, bool sh
         launch_repack(rd, f.matp.p, f.matp32.p, st);
         THM_HIP(hipStreamSynchronize(st));
         f.mat.release();
+        // apply layouts: K_ii^{-1} transposed per cell, F and F^T
+        if (f.n_int > 0) {
+            DBuf<double> kt(f.kiinv.n);
+            launch_batch_transpose(f.n_cells, f.n_int, f.n_int, f.kiinv.p, kt.p, st);
+            THM_HIP(hipMemcpyAsync(f.kiinv.p, kt.p, sizeof(double) * kt.n, hipMemcpyDeviceToDevice, st));
+            THM_HIP(hipStreamSynchronize(st));
+        }
+        f.FT.alloc(f.F.n);
+        launch_batch_transpose(f.n_int > 0 ? f.n_cells : 0, f.ne, f.n_int, f.F.p, f.FT.p, st);
         f.kiinv32.alloc(f.kiinv.n);
         f.F32.alloc(f.F.n);
+        f.FT32.alloc(f.F.n);
         launch_convert(f.kiinv.p, f.kiinv32.p, f.kiinv.n, st);
         launch_convert(f.F.p, f.F32.p, f.F.n, st);
+        launch_convert(f.FT.p, f.FT32.p, f.FT.n, st);
         w.D.release();
         w.Lo0.release();
         w.lo.clear();
@@ -443,7 +454,7 @@ void setup_precond(const std::vector<thm_system *> &all, hipStream_t st, bool sh
     const double dt = now_ms() - t0;
     for (auto &f : facs) {
         f->setup_ms = dt;
-        f->bytes = 12 * (f->matp_elems + (int64_t)f->kiinv.n + (int64_t)f->F.n);
+        f->bytes = 12 * (f->matp_elems + (int64_t)f->kiinv.n + 2 * (int64_t)f->F.n);
     }
 }
 

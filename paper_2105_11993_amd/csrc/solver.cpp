@@ -307,9 +307,11 @@ void Ctx::build_prec() {
         p32[i] = d;
         d.kiinv = f.kiinv.p;
         d.F = f.F.p;
+        d.FT = f.FT.p;
         p64[i] = d;
         p32[i].kiinv = f.kiinv32.p;
         p32[i].F = f.F32.p;
+        p32[i].FT = f.FT32.p;
         soff[i] = so;
         so += 2 * S.L.n_skel_pad;  // planar: real block, then imaginary block
         so = (so + 63) & ~int64_t(63);

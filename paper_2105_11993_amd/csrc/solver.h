@@ -20,8 +20,8 @@ struct Factor {
     int64_t n_cells = 0;
     std::vector<int64_t> pboff;  // padded layer offsets of the skeleton work vectors
     int64_t sp = 0;              // padded skeleton length (one planar half)
-    DBuf<double> kiinv, F;
-    DBuf<float> kiinv32, F32;
+    DBuf<double> kiinv, F, FT;     // kiinv stored transposed per cell after setup (see PrecDesc)
+    DBuf<float> kiinv32, F32, FT32;
     DBuf<double> mat;            // apply matrices during setup (rows x cols, segments packed)
     DBuf<double> matp;           // apply matrices, padded (rows x ld, segments aligned)
     DBuf<float> matp32;
