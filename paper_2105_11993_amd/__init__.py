@@ -38,7 +38,8 @@ class ThmSolveOpts(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("orth", ctypes.c_int32), ("transpose", ctypes.c_int32),
                 ("ddm_outer", ctypes.c_int32), ("inner_rtol", ctypes.c_double), ("max_outer", ctypes.c_int32),
                 ("outer_restart", ctypes.c_int32), ("batched", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("ir_inner_rtol", ctypes.c_double), ("max_refine", ctypes.c_int32), ("krylov", ctypes.c_int32)]
+                ("ir_inner_rtol", ctypes.c_double), ("max_refine", ctypes.c_int32), ("krylov", ctypes.c_int32),
+                ("relax_inner", ctypes.c_int32)]
 
 
 class ThmStats(ctypes.Structure):

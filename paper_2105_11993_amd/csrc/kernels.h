@@ -159,6 +159,7 @@ constexpr int BCR_TAB = 4096;  // 8-column chunks of one task row at most (32768
 struct BcrTask {
     const void *M;             // row-major rows x ld (double or float), 16-byte aligned rows
     int32_t rows, ld, nseg, group;
+    int32_t mbeg, mend;        // the group's members: PrecBatch::memb[mbeg, mend)
     int32_t kq;                // columns per wave (multiple of BCR_KS)
     int32_t nnt;               // 16-wide n tiles per block (1 or 2): members per block = 8 nnt
     int32_t nmc;               // member chunks of the group
@@ -207,6 +208,7 @@ struct PrecBatch {
     DBuf<int64_t> toff;            // complex offset of each system's per-cell condensation terms
     int64_t Ttot = 0;              // complex entries of all condensation terms
     DBuf<int32_t> memb_ptr, memb;  // factor group -> member systems
+    DBuf<int64_t> msoff;           // soff of each entry of memb
     std::vector<PrecPhase> phases; // forward levels, top, backward levels
 };
 

@@ -464,9 +464,11 @@ __global__ void __launch_bounds__(256) k_cond_fwd(const PrecDesc *__restrict__ p
 // A block owns 32 rows (two 16 x 16 MFMA tiles) and up to 16 members; its waves split
 // the columns into contiguous ranges and the partial tiles are summed through LDS in a
 // fixed order, so the result does not depend on scheduling.  Within a 32-column step,
-// lane group g (lanes 16 g .. 16 g + 15) feeds the MFMA k index g with columns
-// k0 + 8 g + j for j = 0..7 (one 16-byte aligned run per lane), row i16 of M and column
-// i16 of X; the sum over k is order-free, so this permutation is exact.
+// lane group g (lanes 16 g .. 16 g + 15) feeds the MFMA k index g, row i16 of M and
+// column i16 of X; its value j (j = h P + t, P = 16 / sizeof(T) values per 16-byte
+// piece) is step column bcr_col(g, j) = 4 P h + P g + t.  The four lane groups thus read
+// 64 contiguous bytes of a row of M or of a column of X per load instruction.  The sum
+// over k is order-free, so this permutation is exact.
 template <class T> struct Mfma;
 // Both forms take A[i][k] from lane i + 16 k and B[k][j] from lane j + 16 k; they
 // differ in where accumulator v of lane j + 16 g sits: row 4 g + v (f32) or row
@@ -486,19 +488,22 @@ template <> struct Mfma<double> {
     static __device__ __forceinline__ int row(int g, int v) { return g + 4 * v; }
 };
 
-// 8 consecutive values from global memory (16-byte aligned), as 16-byte loads.
+// Values per 16-byte piece, and the step column that value j of lane group g carries.
+static_assert(BCR_RT == 32 && BCR_KS == 32, "the lane order of a tile assumes 32 x 32 tiles");
+template <class T> constexpr int bcr_per() { return 16 / (int)sizeof(T); }
 template <class T>
-__device__ __forceinline__ void load8(const T *p, T (&v)[8]) {
+__host__ __device__ constexpr int bcr_col(int g, int j) {
+    return 4 * bcr_per<T>() * (j / bcr_per<T>()) + bcr_per<T>() * g + j % bcr_per<T>();
+}
+
+// One 16-byte aligned piece from global memory: v[h P .. h P + P) = p[0 .. P).
+template <class T>
+__device__ __forceinline__ void load_piece(const T *p, T (&v)[8], int h) {
     typedef T vec16 __attribute__((ext_vector_type(16 / sizeof(T))));
     typedef const __attribute__((address_space(1))) vec16 gvec16;
-    constexpr int per = 16 / sizeof(T);
-    const gvec16 *q = (const gvec16 *)p;
+    const vec16 x = *(const gvec16 *)p;
 #pragma unroll
-    for (int i = 0; i < 8 / per; ++i) {
-        const vec16 x = q[i];
-#pragma unroll
-        for (int j = 0; j < per; ++j) v[i * per + j] = x[j];
-    }
+    for (int t = 0; t < bcr_per<T>(); ++t) v[h * bcr_per<T>() + t] = x[t];
 }
 
 
@@ -522,23 +527,37 @@ struct BcrStep {
 
 // Loads of one step; branch-free so that the next step's loads stay in flight while
 // the current step's MFMAs run.  Lanes of absent members read the chunk's first
-// member (their output columns are never stored).
+// member (their output columns are never stored).  A piece of X lies in one 8-column
+// chunk, whose table entry gives its position in the work vector.
 template <class T, int NNT>
 __device__ __forceinline__ void bcr_fetch_b(BcrStep<T, NNT> &o, const int64_t (&bbase)[NNT], int k, const T *wsb,
                                             const T *ysb) {
-    const int32_t e = bcr_tab[(k >> 3) + ((threadIdx.x >> 4) & 3)];  // this lane group's chunk
-    const T *src = (e & 1) ? ysb : wsb;
-    const int64_t pos = (int64_t)(e >> 1) + k;
+    const int g = (threadIdx.x >> 4) & 3;
 #pragma unroll
-    for (int nt = 0; nt < NNT; ++nt) load8(src + bbase[nt] + pos, o.b[nt]);
+    for (int h = 0; h < 8 / bcr_per<T>(); ++h) {
+        const int c = k + bcr_col<T>(g, h * bcr_per<T>());
+        const int32_t e = bcr_tab[c >> 3];
+        const T *src = (e & 1) ? ysb : wsb;
+        const int64_t pos = (int64_t)(e >> 1) + c;
+#pragma unroll
+        for (int nt = 0; nt < NNT; ++nt) load_piece(src + bbase[nt] + pos, o.b[nt], h);
+    }
+}
+
+// M operands of one step: the row tile is stored in lane order (see k_repack), so piece
+// h of every lane of the wave is one contiguous 64 x 16-byte run.
+template <class T>
+__device__ __forceinline__ void bcr_fetch_a(const T *A, T (&v)[8]) {
+#pragma unroll
+    for (int h = 0; h < 8 / bcr_per<T>(); ++h) load_piece(A + h * 64 * bcr_per<T>(), v, h);
 }
 
 template <class T, int WPB, int NNT>
 __device__ __forceinline__ void bcr_fetch(BcrStep<T, NNT> &o, const BcrShared<T, WPB> &sh,
                                           const int64_t (&bbase)[NNT], const T *A0, const T *A1, int k,
                                           const T *wsb, const T *ysb) {
-    load8(A0 + k, o.a0);
-    load8(A1 + k, o.a1);
+    bcr_fetch_a(A0 + (int64_t)BCR_RT * k, o.a0);  // step k / BCR_KS of the row tile
+    bcr_fetch_a(A1 + (int64_t)BCR_RT * k, o.a1);
     bcr_fetch_b(o, bbase, k, wsb, ysb);
 }
 
@@ -555,22 +574,22 @@ __device__ __forceinline__ void bcr_mma(const BcrStep<T, NNT> &o, typename Mfma<
 
 template <class T, int WPB, int NNT>
 __device__ __forceinline__ void bcr_tile(const BcrTask &tk, BcrShared<T, WPB> &sh, int row0, int mb, int m1,
-                                         const int32_t *__restrict__ memb, const int64_t *__restrict__ soff,
+                                         const int32_t *__restrict__ memb, const int64_t *__restrict__ msoff,
                                          const int32_t *__restrict__ mask, T *__restrict__ wsb,
                                          T *__restrict__ ysb) {
     using V4 = typename Mfma<T>::v4;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i16 = lane & 15, g = lane >> 4;
     const T *M = static_cast<const T *>(tk.M);
-    const int64_t ld = tk.ld;
-    // rows past the end load the last row again; their results are dropped
-    const T *A0 = M + min(row0 + i16, tk.rows - 1) * ld + 8 * g;
-    const T *A1 = M + min(row0 + 16 + i16, tk.rows - 1) * ld + 8 * g;
+    // M is stored tile by tile in lane order (zero rows pad the last row tile): this
+    // lane's values of m tile mt, step k, start at row0 ld + BCR_RT k + 512 mt + P lane
+    const T *A0 = M + (int64_t)row0 * tk.ld + bcr_per<T>() * lane;
+    const T *A1 = A0 + 16 * BCR_KS;
     int64_t bbase[NNT];
 #pragma unroll
     for (int nt = 0; nt < NNT; ++nt) {
         const int mi = mb + 8 * nt + (i16 >> 1);
-        bbase[nt] = soff[memb[mi < m1 ? mi : mb]] + (i16 & 1) * tk.sp + 8 * g;
+        bbase[nt] = msoff[mi < m1 ? mi : mb] + (i16 & 1) * tk.sp;
     }
     V4 acc[2][NNT];
 #pragma unroll
@@ -584,8 +603,8 @@ __device__ __forceinline__ void bcr_tile(const BcrTask &tk, BcrShared<T, WPB> &s
     // X operands need the table).
     BcrStep<T, NNT> p, q;
     if (nst > 0) {
-        load8(A0 + kbeg, p.a0);
-        load8(A1 + kbeg, p.a1);
+        bcr_fetch_a(A0 + (int64_t)BCR_RT * kbeg, p.a0);
+        bcr_fetch_a(A1 + (int64_t)BCR_RT * kbeg, p.a1);
     }
     constexpr int NOUT = BCR_RT * 16 * NNT;
     constexpr int NPT = (NOUT + 64 * WPB - 1) / (64 * WPB);  // outputs per thread
@@ -596,7 +615,7 @@ __device__ __forceinline__ void bcr_tile(const BcrTask &tk, BcrShared<T, WPB> &s
             const int n = o / BCR_RT, r = o % BCR_RT;
             const int mi = mb + (n >> 1);
             if (o < NOUT && row0 + r < tk.rows && mi < m1)
-                sh.yold[o] = ((tk.out_dst ? ysb : wsb) + soff[memb[mi]] + (n & 1) * tk.sp + tk.out_off)[row0 + r];
+                sh.yold[o] = ((tk.out_dst ? ysb : wsb) + msoff[mi] + (n & 1) * tk.sp + tk.out_off)[row0 + r];
         }
     }
     for (int kc = threadIdx.x; kc < (tk.ld >> 3); kc += blockDim.x) bcr_tab[kc] = tk.tab[kc];
@@ -651,12 +670,11 @@ __device__ __forceinline__ void bcr_tile(const BcrTask &tk, BcrShared<T, WPB> &s
         const int n = o / BCR_RT, r = o % BCR_RT;
         const int mi = mb + (n >> 1);
         if (o >= NOUT || row0 + r >= tk.rows || mi >= m1) continue;
-        const int s = memb[mi];
-        if (mask && !mask[s]) continue;
+        if (mask && !mask[memb[mi]]) continue;
         T v = 0;
 #pragma unroll
         for (int w = 0; w < H; ++w) v += sh.red[w][n][r];
-        T *y = (tk.out_dst ? ysb : wsb) + soff[s] + (n & 1) * tk.sp + tk.out_off + row0 + r;
+        T *y = (tk.out_dst ? ysb : wsb) + msoff[mi] + (n & 1) * tk.sp + tk.out_off + row0 + r;
         *y = tk.subtract ? sh.yold[o] - v : v;
     }
 }
@@ -668,9 +686,8 @@ template <> struct BcrOcc<double> { static constexpr int v = 2; };
 template <class T, int WPB>
 __global__ void __launch_bounds__(64 * WPB, BcrOcc<T>::v) k_bcr_mfma(const BcrTask *__restrict__ tasks,
                                                        const int32_t *__restrict__ blkoff, int ntasks,
-                                                       const int32_t *__restrict__ memb_ptr,
                                                        const int32_t *__restrict__ memb,
-                                                       const int64_t *__restrict__ soff,
+                                                       const int64_t *__restrict__ msoff,
                                                        const int32_t *__restrict__ mask, T *__restrict__ wsb,
                                                        T *__restrict__ ysb) {
     __shared__ BcrShared<T, WPB> sh;
@@ -684,16 +701,16 @@ __global__ void __launch_bounds__(64 * WPB, BcrOcc<T>::v) k_bcr_mfma(const BcrTa
     const BcrTask &tk = tasks[t];
     const int local = lb - blkoff[t];
     const int rt = local / tk.nmc, mchunk = local - rt * tk.nmc;
-    const int m1 = memb_ptr[tk.group + 1];
-    const int mb = memb_ptr[tk.group] + mchunk * 8 * tk.nnt;
+    const int m1 = tk.mend;
+    const int mb = tk.mbeg + mchunk * 8 * tk.nnt;
     // any active member in this chunk: one flag per lane, the same ballot in every wave
     const int lane = threadIdx.x & 63;
     const bool on = lane < 8 * tk.nnt && mb + lane < m1 && (!mask || mask[memb[mb + lane]]);
     if (!__ballot(on)) return;  // same decision in every thread of the block
     if (tk.nnt == 1)
-        bcr_tile<T, WPB, 1>(tk, sh, rt * BCR_RT, mb, m1, memb, soff, mask, wsb, ysb);
+        bcr_tile<T, WPB, 1>(tk, sh, rt * BCR_RT, mb, m1, memb, msoff, mask, wsb, ysb);
     else
-        bcr_tile<T, WPB, 2>(tk, sh, rt * BCR_RT, mb, m1, memb, soff, mask, wsb, ysb);
+        bcr_tile<T, WPB, 2>(tk, sh, rt * BCR_RT, mb, m1, memb, msoff, mask, wsb, ysb);
 }
 
 // x[g] = ys[pos(g)] on skeleton DoFs; interiors: x_i = Kii^{-1} r_i - F^T x_e.
@@ -746,7 +763,7 @@ void launch_bcr_phases(const PrecBatch &P, const int32_t *mask, T *ws, T *ys, hi
         const int nb = ph.sched[prec].nblocks;
         if (!nb) continue;
         k_bcr_mfma<T, BCR_WPB><<<nb, 64 * BCR_WPB, sizeof(int32_t) * (ph.max_ld / 8), st>>>(
-            ph.tasks[prec].p, ph.sched[prec].blkoff.p, ph.ntasks, P.memb_ptr.p, P.memb.p, P.soff.p, mask, ws, ys);
+            ph.tasks[prec].p, ph.sched[prec].blkoff.p, ph.ntasks, P.memb.p, P.msoff.p, mask, ws, ys);
     }
     THM_HIP(hipGetLastError());
 }
@@ -771,30 +788,56 @@ void launch_batch_transpose(int64_t count, int rows, int cols, const double *src
 }
 
 // ------------------------------------------------------------------ padded copies (setup)
+// Element (r, c) of the padded apply matrix (zero outside the true rows and segments).
+__device__ double repack_value(const RepackDesc &d, int64_t r, int pc) {
+    if (r >= d.rows) return 0.0;
+    for (int q = 0; q < d.nseg; ++q) {
+        const int j = pc - d.seg_pstart[q];
+        if (j >= 0 && j < d.seg_len[q]) return d.src[r * d.cols + d.seg_col[q] + j];
+    }
+    return 0.0;
+}
+
+// Row and column of slot w of a BCR_RT x BCR_KS tile stored in lane order for values of
+// P per 16-byte piece: m tile mt = w / 512, then piece h, lane L = i16 + 16 g, value t,
+// holding row 16 mt + i16 and step column bcr_col(g, h P + t).
+template <class T>
+__device__ void repack_slot(int w, int &r, int &c) {
+    constexpr int P = bcr_per<T>();
+    const int mt = w / 512, w2 = w % 512;
+    const int h = w2 / (64 * P), L = (w2 % (64 * P)) / P, t = w2 % P;
+    r = 16 * mt + L % 16;
+    c = bcr_col<T>(L / 16, h * P + t);
+}
+
+// Copy of the apply matrices in the layout the MFMA apply streams: rows rounded up to
+// BCR_RT, the columns of each segment at its padded start, cut into BCR_RT x BCR_KS
+// tiles stored one after another along a row tile, each tile in lane order.  A wave's
+// operand loads of one step are then contiguous runs, and its column range one stream.
 __global__ void __launch_bounds__(256) k_repack(const RepackDesc *__restrict__ ds, const int32_t *__restrict__ blkoff,
                                                 int nd, double *__restrict__ dst64, float *__restrict__ dst32) {
     const int di = find_sys2(blkoff, nd, blockIdx.x);
     const RepackDesc &d = ds[di];
     const int64_t e = (int64_t)(blockIdx.x - blkoff[di]) * 256 + threadIdx.x;
-    if (e >= (int64_t)d.rows * d.ld) return;
-    const int64_t r = e / d.ld;
-    const int pc = (int)(e - r * d.ld);
-    double v = 0.0;
-    for (int q = 0; q < d.nseg; ++q) {
-        const int j = pc - d.seg_pstart[q];
-        if (j >= 0 && j < d.seg_len[q]) {
-            v = d.src[r * d.cols + d.seg_col[q] + j];
-            break;
-        }
-    }
-    dst64[d.poff + e] = v;
-    dst32[d.poff + e] = (float)v;
+    const int64_t prows = (int64_t)(d.rows + BCR_RT - 1) / BCR_RT * BCR_RT;
+    if (e >= prows * d.ld) return;
+    constexpr int TS = BCR_RT * BCR_KS;
+    const int64_t tile = e / TS;
+    const int w = (int)(e - tile * TS);
+    const int nk = d.ld / BCR_KS;
+    const int64_t rt = tile / nk;
+    const int kc = (int)(tile - rt * nk);
+    int r, c;
+    repack_slot<double>(w, r, c);
+    dst64[d.poff + e] = repack_value(d, rt * BCR_RT + r, kc * BCR_KS + c);
+    repack_slot<float>(w, r, c);
+    dst32[d.poff + e] = (float)repack_value(d, rt * BCR_RT + r, kc * BCR_KS + c);
 }
 
 void launch_repack(const std::vector<RepackDesc> &d, double *dst64, float *dst32, hipStream_t st) {
     if (d.empty()) return;
     std::vector<int64_t> units(d.size());
-    for (size_t i = 0; i < d.size(); ++i) units[i] = (int64_t)d[i].rows * d[i].ld;
+    for (size_t i = 0; i < d.size(); ++i) units[i] = (int64_t)(d[i].rows + BCR_RT - 1) / BCR_RT * BCR_RT * d[i].ld;
     Sched sc;
     sc.build(units, 256, st);
     DBuf<RepackDesc> dd;

@@ -150,7 +150,8 @@ static void plan(Factor &f) {
     off += (int64_t)f.top_n * f.top_n;
     f.mat_elems = off;
     // padded copies for the apply: each input segment starts at its layer's aligned
-    // width, rows are padded to a multiple of the MFMA column step
+    // width, the row length is padded to a multiple of the MFMA column step and the row
+    // count to a multiple of the row tile; stored tile by tile (see k_repack)
     int64_t poff = 0;
     auto pad = [&](Factor::Blk &b) {
         int c = 0;
@@ -164,7 +165,7 @@ static void plan(Factor &f) {
         if (b.ld > 8 * BCR_TAB)
             fail(THM_EUNSUPPORTED, "a cyclic-reduction block has more columns than the apply kernel supports");
         b.poff = poff;
-        poff += (int64_t)b.rows * b.ld;
+        poff += (int64_t)(b.rows + BCR_RT - 1) / BCR_RT * BCR_RT * b.ld;
     };
     for (auto &lev : f.fwd)
         for (auto &b : lev) pad(b);

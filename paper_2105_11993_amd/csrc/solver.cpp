@@ -336,14 +336,18 @@ void Ctx::build_prec() {
         P.toff.upload(toff, st);
         P.Ttot = std::max<int64_t>(to, 1);
     }
+    std::vector<int32_t> mp_host(1, 0);
     {
-        std::vector<int32_t> mp(1, 0), mm;
+        std::vector<int32_t> &mp = mp_host, mm;
         for (auto &v : members) {
             mm.insert(mm.end(), v.begin(), v.end());
             mp.push_back((int32_t)mm.size());
         }
         P.memb_ptr.upload(mp, st);
         P.memb.upload(mm, st);
+        std::vector<int64_t> ms(mm.size());
+        for (size_t i = 0; i < mm.size(); ++i) ms[i] = soff.at(mm[i]);
+        P.msoff.upload(ms, st);
     }
     // cyclic-reduction phases: forward levels, last blocks, backward levels
     int nlev = 0;
@@ -355,6 +359,8 @@ void Ctx::build_prec() {
         t.ld = b.ld;
         t.nseg = b.nseg;
         t.group = g;
+        t.mbeg = mp_host[g];
+        t.mend = mp_host[g + 1];
         t.kq = ((b.ld + BCR_WPB - 1) / BCR_WPB + BCR_KS - 1) / BCR_KS * BCR_KS;
         const int nm = (int)members[g].size();
         t.nnt = nm > 8 ? 2 : 1;
@@ -414,6 +420,13 @@ void Ctx::build_prec() {
         ph.tasks[1].upload(t32, st);
         ph.sched[0].build(u64, 1, st);
         ph.sched[1].build(u32, 1, st);
+        if (std::getenv("THM_PROGRESS")) {
+            int64_t rows = 0, nb = 0;
+            for (size_t i = 0; i < t32.size(); ++i) rows += t32[i].rows, nb += u32[i];
+            std::fprintf(stderr, "[thm]   apply phase %zu: %d tasks, %lld rows, widest %d columns, %lld blocks, %.1f MB (FP32)\n",
+                         P.phases.size() - 1, ph.ntasks, (long long)rows, ph.max_ld, (long long)nb,
+                         bcr_bytes[1].back() * 1e-6);
+        }
     };
     for (int lev = 0; lev < nlev; ++lev)
         add_phase([&](const Factor &f) {
