@@ -808,7 +808,7 @@ static void ddm_solve_impl(thm_system &G, const thm_solve_opts &o, double *E, th
                     THM_HIP(hipMemcpy(&r, D.outer->est.p, sizeof(double), hipMemcpyDeviceToHost));
                     if (!(r > 0.0) || !(r < 1.0)) r = 1.0;
                 }
-                run.inner_o.rtol = std::max(o.inner_rtol, std::min(1e-6, 1e-3 * gp.rtol / r));
+                run.inner_o.rtol = std::max(o.inner_rtol, std::min(1e-4, 1e-2 * gp.rtol / r));
             }
             run.inner_solve(x, false);
             run.update(x, 1, b ? D.tmp.p : y);
