@@ -105,7 +105,7 @@ template <class T>
 void launch_norm2(const Batch &B, const int32_t *mask, const T *x, double *part, hipStream_t st);
 template <class TI, class TO>
 void launch_scale(const Batch &B, const int32_t *mask, const double *scal, int invert, const TI *x, TO *y1,
-                  const int32_t *jcol, int64_t ld1, TO *y2, hipStream_t st);
+                  const int32_t *jcol, int64_t ld1, TO *y2, hipStream_t st, int32_t *step_ctr = nullptr);
 template <class T>
 void launch_lincomb(const Batch &B, const int32_t *mask, const int32_t *kcnt, const T *V, int64_t ld,
                     const double *coef, int ldc, T *y, hipStream_t st);
@@ -121,7 +121,7 @@ void launch_cycle_start(const Batch &B, const double *part, int32_t *running, in
 void launch_arnoldi_finish(const Batch &B, const double *part, int32_t *active, int32_t *jcnt, const double *hcol,
                            int ldh, double *H, double *cs, double *sn, double *g, double *hnext,
                            const double *bnorm, const double *rtol_d, int m, int32_t *iters, int max_iter,
-                           double *est, hipStream_t st);
+                           double *est, int32_t *hflags, const int32_t *step_ctr, int nslots, hipStream_t st);
 void launch_hsolve(const Batch &B, const int32_t *running, const int32_t *jcnt, const double *H, const double *g,
                    double *y, int m, hipStream_t st);
 template <class T>

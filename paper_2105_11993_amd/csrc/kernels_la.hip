@@ -383,13 +383,16 @@ __global__ void __launch_bounds__(256) k_norm2(const int64_t *__restrict__ off, 
     wave_store<T>(a, part + ((int64_t)blockIdx.x * NPW + (threadIdx.x >> 6)) * maxcols);
 }
 
-// y = a_s * x (a_s = scal[s] or 1/scal[s]); optional second destination.
+// y = a_s * x (a_s = scal[s] or 1/scal[s]); optional second destination.  The last
+// kernel of an Arnoldi step also advances the step counter (step_ctr, one thread).
 template <class TI, class TO>
 __global__ void __launch_bounds__(256) k_scale(const int64_t *__restrict__ off, const int64_t *__restrict__ len,
                                                const int32_t *__restrict__ blkoff, int ns,
                                                const int32_t *__restrict__ mask, const double *__restrict__ scal,
                                                int invert, const TI *__restrict__ x, TO *__restrict__ y1,
-                                               const int32_t *__restrict__ jcol, int64_t ld1, TO *__restrict__ y2) {
+                                               const int32_t *__restrict__ jcol, int64_t ld1, TO *__restrict__ y2,
+                                               int32_t *__restrict__ step_ctr) {
+    if (step_ctr && blockIdx.x == 0 && threadIdx.x == 0) *step_ctr += 1;
     const int s = find_sys(blkoff, ns, blockIdx.x);
     if (mask && !mask[s]) return;
     const int64_t base = off[s], n = len[s];
@@ -516,10 +519,17 @@ __global__ void k_arnoldi_finish(int ns, const int32_t *__restrict__ blkoff, con
                                  double *__restrict__ cs, double *__restrict__ sn, double *__restrict__ g,
                                  double *__restrict__ hnext, const double *__restrict__ bnorm,
                                  const double *__restrict__ rtol_d, int m, int32_t *__restrict__ iters, int max_iter,
-                                 double *__restrict__ resid_est) {
+                                 double *__restrict__ resid_est, int32_t *__restrict__ hflags,
+                                 const int32_t *__restrict__ step_ctr, int nslots) {
     __shared__ double colr[1025], coli[1025], csl[1024], snr[1024], sni[1024];
     const int s = blockIdx.x;
-    if (s >= ns || !active[s]) return;
+    if (s >= ns) return;
+    // the system's flag after this step, also written to host memory (slot of the step)
+    int32_t *hf = hflags + (int64_t)(*step_ctr % nslots) * ns + s;
+    if (!active[s]) {
+        if (threadIdx.x == 0) *hf = 0;
+        return;
+    }
     const int j = jcnt[s];
     const double hn = sqrt(slot_sum(part, maxcols, blkoff[s], blkoff[s + 1], 0));
     const double *hc = hcol + (int64_t)s * ldh;
@@ -585,7 +595,9 @@ __global__ void k_arnoldi_finish(int ns, const int32_t *__restrict__ blkoff, con
         const double est = hypot(gs[2 * (j + 1)], gs[2 * (j + 1) + 1]) / bnorm[s];
         resid_est[s] = est;
         const bool breakdown = !(hn > 1e-300) || !(den > 0.0);
-        if (est <= *rtol_d || breakdown || j + 1 >= m || iters[s] >= max_iter || !isfinite(est)) active[s] = 0;
+        const int32_t on = !(est <= *rtol_d || breakdown || j + 1 >= m || iters[s] >= max_iter || !isfinite(est));
+        active[s] = on;
+        *hf = on;
     }
     __syncthreads();
     double *Hs = H + (int64_t)s * 2 * (m + 1) * m + (int64_t)j * 2 * (m + 1);  // column j, complex
@@ -686,9 +698,10 @@ void launch_norm2(const Batch &B, const int32_t *mask, const T *x, double *part,
 }
 template <class TI, class TO>
 void launch_scale(const Batch &B, const int32_t *mask, const double *scal, int invert, const TI *x, TO *y1,
-                  const int32_t *jcol, int64_t ld1, TO *y2, hipStream_t st) {
+                  const int32_t *jcol, int64_t ld1, TO *y2, hipStream_t st, int32_t *step_ctr) {
     VGUARD(B);
-    k_scale<TI, TO><<<VGRID(B.vs)>>>(B.off.p, B.len.p, B.vs.blkoff.p, B.ns, mask, scal, invert, x, y1, jcol, ld1, y2);
+    k_scale<TI, TO><<<VGRID(B.vs)>>>(B.off.p, B.len.p, B.vs.blkoff.p, B.ns, mask, scal, invert, x, y1, jcol, ld1, y2,
+                                     step_ctr);
     THM_HIP(hipGetLastError());
 }
 template <class T>
@@ -727,11 +740,11 @@ void launch_cycle_start(const Batch &B, const double *part, int32_t *running, in
 void launch_arnoldi_finish(const Batch &B, const double *part, int32_t *active, int32_t *jcnt, const double *hcol,
                            int ldh, double *H, double *cs, double *sn, double *g, double *hnext,
                            const double *bnorm, const double *rtol_d, int m, int32_t *iters, int max_iter,
-                           double *est, hipStream_t st) {
+                           double *est, int32_t *hflags, const int32_t *step_ctr, int nslots, hipStream_t st) {
     if (m > 1024) fail(THM_EINVAL, "restart must be <= 1024");
     k_arnoldi_finish<<<B.ns, 64, 0, st>>>(B.ns, B.vs.blkoff.p, part, B.maxcols, active, jcnt, hcol,
                                                       ldh, H, cs, sn, g, hnext, bnorm, rtol_d, m, iters, max_iter,
-                                                      est);
+                                                      est, hflags, step_ctr, nslots);
     THM_HIP(hipGetLastError());
 }
 void launch_hsolve(const Batch &B, const int32_t *running, const int32_t *jcnt, const double *H, const double *g,
@@ -758,13 +771,13 @@ void launch_zero_flagged(const Batch &B, const uint8_t *const *dirs, T *x, hipSt
 INST_T(double)
 INST_T(float)
 template void launch_scale<double, double>(const Batch &, const int32_t *, const double *, int, const double *,
-                                           double *, const int32_t *, int64_t, double *, hipStream_t);
+                                           double *, const int32_t *, int64_t, double *, hipStream_t, int32_t *);
 template void launch_scale<float, float>(const Batch &, const int32_t *, const double *, int, const float *,
-                                         float *, const int32_t *, int64_t, float *, hipStream_t);
+                                         float *, const int32_t *, int64_t, float *, hipStream_t, int32_t *);
 template void launch_scale<float, double>(const Batch &, const int32_t *, const double *, int, const float *,
-                                          double *, const int32_t *, int64_t, double *, hipStream_t);
+                                          double *, const int32_t *, int64_t, double *, hipStream_t, int32_t *);
 template void launch_scale<double, float>(const Batch &, const int32_t *, const double *, int, const double *,
-                                          float *, const int32_t *, int64_t, float *, hipStream_t);
+                                          float *, const int32_t *, int64_t, float *, hipStream_t, int32_t *);
 template void launch_axpy<double, double>(const Batch &, const int32_t *, const double *, const double *, double *,
                                           hipStream_t);
 template void launch_axpy<float, float>(const Batch &, const int32_t *, const double *, const float *, float *,

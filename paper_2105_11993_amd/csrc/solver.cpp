@@ -46,7 +46,10 @@ void Krylov::init(const std::vector<int64_t> &n, int m_, hipStream_t st) {
     part.alloc((size_t)std::max(1, B.vs.nblocks) * NPW * B.maxcols);
     for (DBuf<int32_t> *b : {&running, &active, &jcnt, &iters}) b->alloc(ns);
     if (pinned) (void)hipHostFree(pinned);
-    THM_HIP(hipHostMalloc((void **)&pinned, sizeof(int32_t) * NEV * std::max(ns, 1)));
+    THM_HIP(hipHostMalloc((void **)&pinned, sizeof(int32_t) * NEV * std::max(ns, 1),
+                          hipHostMallocMapped | hipHostMallocCoherent));
+    THM_HIP(hipHostGetDevicePointer((void **)&pinned_dev, pinned, 0));
+    step_ctr.alloc(1);
     for (auto &e : ev)
         if (!e) THM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
 }
@@ -116,8 +119,9 @@ static void arnoldi_step(Krylov &K, const KOps<T> &ops, const GmresParams &p, hi
         launch_cgs_update<T>(B, act, K.jcnt.p, V, B.Ltot, w, K.hcol2.p, ldh, K.part.p, st);
     }
     launch_arnoldi_finish(B, K.part.p, act, K.jcnt.p, K.hcol.p, ldh, K.H.p, K.cs.p, K.sn.p, K.g.p, K.hnext.p,
-                          K.bnorm.p, K.rtol_d.p, m, K.iters.p, p.max_iter, K.est.p, st);
-    launch_scale<T, T>(B, act, K.hnext.p, 1, w, V, K.jcnt.p, B.Ltot, cur, st);
+                          K.bnorm.p, K.rtol_d.p, m, K.iters.p, p.max_iter, K.est.p, K.pinned_dev, K.step_ctr.p,
+                          Krylov::NEV, st);
+    launch_scale<T, T>(B, act, K.hnext.p, 1, w, V, K.jcnt.p, B.Ltot, cur, st, K.step_ctr.p);
 }
 
 template <class T>
@@ -181,14 +185,15 @@ void gmres_run(Krylov &K, const KOps<T> &ops, const T *b, T *x, const int32_t *m
         THM_HIP(hipStreamSynchronize(st));
         if (!any_set(hflag[0], ns)) break;
         launch_scale<T, T>(B, K.active.p, K.beta.p, 1, w, V, K.jcnt.p, B.Ltot, cur, st);
-        // Arnoldi steps; the host checks the flags of step j - LAG while later steps run.
+        // Arnoldi steps; the finish kernel of step j writes the systems' flags to host slot
+        // j mod NEV, and the host checks the flags of step j - LAG while later steps run.
+        THM_HIP(hipMemsetAsync(K.step_ctr.p, 0, sizeof(int32_t), st));
         constexpr int LAG = 3;
+        static_assert(LAG + 1 < Krylov::NEV, "flag slots in flight must not wrap");
         for (int step = 0; step < m; ++step) {
             if (exec) THM_HIP(hipGraphLaunch(exec, st));
             else arnoldi_step<T>(K, ops, p, st);
             const int sl = step % Krylov::NEV;
-            THM_HIP(hipMemcpyAsync(K.pinned + (size_t)sl * ns, K.active.p, sizeof(int32_t) * ns,
-                                   hipMemcpyDeviceToHost, st));
             THM_HIP(hipEventRecord(K.ev[sl], st));
             if (step >= LAG) {
                 const int ol = (step - LAG) % Krylov::NEV;

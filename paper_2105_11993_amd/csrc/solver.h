@@ -101,7 +101,9 @@ struct Krylov {
     DBuf<double> V64, w64, z64, cur64;
     DBuf<float> V32, w32, z32, cur32;
     static constexpr int NEV = 8;
-    int32_t *pinned = nullptr;  // NEV x ns host flags
+    int32_t *pinned = nullptr;  // NEV x ns host flags (coherent host memory, written by kernels)
+    int32_t *pinned_dev = nullptr;  // the same memory as seen by kernels
+    DBuf<int32_t> step_ctr;     // Arnoldi steps of the current cycle (selects the flag slot)
     hipEvent_t ev[NEV] = {};
     struct GraphSlot {
         hipGraphExec_t exec = nullptr;
