@@ -93,7 +93,10 @@ typedef struct {
                                 subdomain tolerance is max(inner_rtol, min(1e-4, 1e-2 rtol / r)) with r the
                                 outer GMRES's current relative residual estimate (inexact Krylov
                                 relaxation: late outer steps tolerate less accurate subdomain solves; the
-                                returned field still meets rtol in the global FP64 residual); 0 = inner_rtol
+                                returned field still meets rtol in the global FP64 residual). Suited to outer
+                                iterations that converge in few steps: where the outer operator is ill
+                                conditioned the outer residual estimate can stall above rtol, and the outer
+                                GMRES then runs to max_outer before the final check; 0 = inner_rtol
                                 throughout (0) */
 } thm_solve_opts;
 
