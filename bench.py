@@ -35,6 +35,8 @@ def parse():
     ap.add_argument("--count", type=int, default=256, help="c4: number of problems")
     ap.add_argument("--scale", type=int, default=1, help="c4: divide every mesh size by this")
     ap.add_argument("--skip-plain", action="store_true")
+    ap.add_argument("--skip-full", action="store_true",
+                    help="skip the complete-inverse preconditioner ablation (c2)")
     ap.add_argument("--restart", type=int, default=64)
     ap.add_argument("--max-outer", type=int, default=500, help="cap on outer iterations (profiling runs)")
     ap.add_argument("--inner-rtol", type=float, default=1e-10,
@@ -325,6 +327,30 @@ def main():
                         "rel_residual": stp["rel_residual"]}
         log(args, f"plain fp64: {result_plain}")
 
+    # ablation: the complete inverse of the block system (Sec. 3.2's alternative) as the
+    # subdomain preconditioner, applied exactly through K^{-1} and a boundary correction
+    result_full = None
+    if not args.only_fast and not args.skip_full and args.workload == "c2":
+        result_full = {"preconditioner": "complete inverse (K + iC)^{-1}: K^{-1} plus the boundary correction "
+                                         "(THM_PREC_FULL); an ablation, not the benchmark form"}
+        stf = None
+        for name, prec in (("fp32_refine", thm.THM_FP32_IR), ("fp64", thm.THM_FP64)):
+            of = thm.default_opts(precision=prec, batched=1, use_graph=1, ir_inner_rtol=1e-6,
+                                  precond=thm.THM_PREC_FULL, **common)
+            t0 = time.perf_counter()
+            thm.thm_ddm_solve(S, of, E=E, allow_not_converged=True)  # the first call builds M^{-1}
+            torch.cuda.synchronize()
+            t_first = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            _, stf = thm.thm_ddm_solve(S, of, E=E, allow_not_converged=True)
+            torch.cuda.synchronize()
+            result_full[name] = {"s": time.perf_counter() - t0, "first_call_s": t_first,
+                                 "outer_iters": stf["outer_iters"], "inner_iters": stf["iters"],
+                                 "rel_residual": stf["rel_residual"]}
+        result_full["extra_bytes"] = stf["precond_extra_bytes"]
+        result_full["factor_bytes"] = S.fresh_info()["factor_bytes"]
+        log(args, f"complete inverse: {result_full}")
+
     # block-SpMV bandwidth on the global operator (HIP events on the library's stream)
     spmv = {}
     for name, prec in (("fp64", thm.THM_FP64), ("fp32", thm.THM_FP32_IR)):
@@ -365,6 +391,7 @@ def main():
         "batched_fp64": result_b64,
         "plain_fp64": result_plain,
         "speedup_vs_plain_fp64": (result_plain["s"] / t_fast) if result_plain else None,
+        "full_inverse_ablation": result_full,
         "spmv": spmv,
         "roofline": roof,
         "device_copy": copy,

@@ -54,6 +54,14 @@ typedef enum { THM_ORTH_CGS = 0, THM_ORTH_CGS2 = 1 } thm_orth;
  * the interleaved (re, im) pairs), i.e. the Krylov space is closed under
  * multiplication by i.  Operator, preconditioner and solution are the same. */
 typedef enum { THM_KRYLOV_COMPLEX = 0, THM_KRYLOV_REAL = 1 } thm_krylov;
+/* Preconditioner of the subdomain / single-domain GMRES.  THM_PREC_BLOCK is the paper's
+ * block-diagonal diag(K, K)^{-1} (eq. (11)).  THM_PREC_FULL is the complete inverse of the
+ * block system, which Sec. 3.2 names as the alternative: here (K + iC)^{-1} (transpose:
+ * (K - iC)^{-1}) applied exactly as z - K^{-1} P^T M^{-1} (i C_G P z), z = K^{-1} b, where P
+ * restricts to the boundary DoFs Gamma that carry C, C_G is C on Gamma and
+ * M = I + i C_G P K^{-1} P^T (r x r complex, r = |Gamma|; stored once per distinct system).
+ * One application costs two applications of K^{-1} plus an r x r complex product. */
+typedef enum { THM_PREC_BLOCK = 0, THM_PREC_FULL = 1 } thm_precond;
 
 /* Problem statement (paper Sec. 2, eq. (1); partition eq. (5)).  Copied by thm_assemble. */
 typedef struct {
@@ -98,6 +106,7 @@ typedef struct {
                                 conditioned the outer residual estimate can stall above rtol, and the outer
                                 GMRES then runs to max_outer before the final check; 0 = inner_rtol
                                 throughout (0) */
+    int32_t precond;         /* thm_precond (THM_PREC_BLOCK) */
 } thm_solve_opts;
 
 typedef struct {
@@ -111,6 +120,8 @@ typedef struct {
     int32_t fp64_fallback;   /* THM_FP32_IR: solves finished by FP64 GMRES because a refinement step did not
                                 halve the FP64 residual or max_refine was reached (DDM: summed over the
                                 subdomain solves); 0 otherwise */
+    int64_t precond_extra_bytes; /* THM_PREC_FULL: device bytes of the stored M^{-1} (FP64 + FP32) of the
+                                context that solved (all subdomains for the DDM); 0 otherwise */
 } thm_stats;
 
 typedef struct {
@@ -196,6 +207,14 @@ thm_status thm_apply_operator(thm_system *sys, int32_t transpose, int32_t precis
 /* y = diag(K, K)^{-1} x (eq. (11)), exact factorised inverse; factorises on first use. */
 thm_status thm_apply_precond(thm_system *sys, int32_t precision, const void *x_dev, void *y_dev,
                              void *stream);
+/* y = (K + iC)^{-1} x (transpose = 0) or (K - iC)^{-1} x (transpose = 1): the complete
+ * inverse of the block system (Sec. 3.2; see THM_PREC_FULL), in the real block form of
+ * eq. (4), x and y complex128[n_dofs] on the device (interleaved re, im).  Builds the
+ * factorisation and the boundary correction on first use.  precision THM_FP32_IR applies
+ * it in FP32 (input and output still FP64).
+ * Errors: THM_EINVAL (null arguments), THM_ESINGULAR (singular I + i C_G S_G), THM_EHIP. */
+thm_status thm_apply_precond_full(thm_system *sys, int32_t transpose, int32_t precision, const void *x_dev,
+                                  void *y_dev, void *stream);
 /* Copy the assembled (not Dirichlet-modified) matrices to host memory.  Arrays
  * of sizes n_dofs+1 / nnz / nnz / n_dofs+1 / nnz_c / nnz_c; any may be NULL. */
 thm_status thm_export_matrices(thm_system *sys, int32_t *k_rowptr, int32_t *k_col, double *k_val,

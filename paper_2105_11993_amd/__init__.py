@@ -21,6 +21,7 @@ THM_FP64, THM_FP32_IR = 0, 1
 THM_DDM_GMRES, THM_DDM_JACOBI = 0, 1
 THM_ORTH_CGS, THM_ORTH_CGS2 = 0, 1
 THM_KRYLOV_COMPLEX, THM_KRYLOV_REAL = 0, 1
+THM_PREC_BLOCK, THM_PREC_FULL = 0, 1
 
 _d3 = ctypes.c_double * 3
 _i3 = ctypes.c_int32 * 3
@@ -39,13 +40,14 @@ class ThmSolveOpts(ctypes.Structure):
                 ("ddm_outer", ctypes.c_int32), ("inner_rtol", ctypes.c_double), ("max_outer", ctypes.c_int32),
                 ("outer_restart", ctypes.c_int32), ("batched", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("ir_inner_rtol", ctypes.c_double), ("max_refine", ctypes.c_int32), ("krylov", ctypes.c_int32),
-                ("relax_inner", ctypes.c_int32)]
+                ("relax_inner", ctypes.c_int32), ("precond", ctypes.c_int32)]
 
 
 class ThmStats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("outer_iters", ctypes.c_int32),
                 ("refinements", ctypes.c_int32), ("rel_residual", ctypes.c_double), ("setup_ms", ctypes.c_double),
-                ("solve_ms", ctypes.c_double), ("fp64_fallback", ctypes.c_int32)]
+                ("solve_ms", ctypes.c_double), ("fp64_fallback", ctypes.c_int32),
+                ("precond_extra_bytes", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -61,7 +63,7 @@ class ThmInfo(ctypes.Structure):
 EXPORTS = ["thm_default_opts", "thm_assemble", "thm_gmres_solve", "thm_ddm_solve", "thm_adjoint_grad",
            "thm_system_info", "thm_system_set_mu", "thm_system_destroy", "thm_last_error", "thm_apply_operator",
            "thm_apply_precond", "thm_export_matrices", "thm_export_rhs", "thm_export_elements", "thm_time_spmv",
-           "thm_time_precond", "thm_set_spmv_variant"]
+           "thm_time_precond", "thm_set_spmv_variant", "thm_apply_precond_full"]
 THM_SPMV_SELL = 19
 SPMV_VARIANTS = [21, 41, 81, 161, 321, 641, 24, 44, 84, 164, 324, THM_SPMV_SELL]
 
@@ -90,6 +92,7 @@ def load_library(path=LIB_PATH):
         "thm_time_spmv": (i32, [vp, i32, i32, dp, dp, vp]),
         "thm_time_precond": (i32, [vp, i32, i32, dp, dp, ctypes.POINTER(i32), vp]),
         "thm_set_spmv_variant": (i32, [vp, i32, i32]),
+        "thm_apply_precond_full": (i32, [vp, i32, i32, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -275,6 +278,16 @@ def thm_apply_precond(system, x, precision=THM_FP64, stream=None):
     y = torch.empty_like(_cvec(system.n, x))
     _check(_lib.thm_apply_precond(system.handle, int(precision), ctypes.c_void_p(x.data_ptr()),
                                   ctypes.c_void_p(y.data_ptr()), _stream(stream)))
+    return y
+
+
+def thm_apply_precond_full(system, x, transpose=False, precision=THM_FP64, stream=None):
+    """y = (K + iC)^{-1} x, or (K - iC)^{-1} x with transpose (complete inverse, THM_PREC_FULL)."""
+    torch = _torch()
+    y = torch.empty_like(_cvec(system.n, x))
+    _check(_lib.thm_apply_precond_full(system.handle, int(bool(transpose)), int(precision),
+                                       ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                       _stream(stream)))
     return y
 
 

@@ -220,6 +220,29 @@ template <class T>
 void launch_prec_apply(const PrecBatch &P, const PrecDesc *d, const int64_t *off, int ns, const int32_t *mask,
                        const T *r, T *x, T *ws, T *ys, T *tw, hipStream_t st);
 
+// ---- complete inverse (K + iC)^{-1} through K^{-1} and a boundary correction (kernels_full.hip)
+struct FullDesc {
+    int maxr = 0, nchmax = 0;        // largest boundary size; column chunks of M^{-1} per row
+    const int64_t *goff = nullptr;   // ns + 1: system s owns Gamma entries [goff[s], goff[s + 1])
+    const int32_t *gam = nullptr;    // boundary DoFs (complex index within the system)
+    const int32_t *cptr = nullptr;   // C_G rows: entries [cptr[g], cptr[g + 1]) of row g (absolute)
+    const int32_t *ccol = nullptr;   // Gamma-local columns of C_G
+    const void *cval64 = nullptr, *cval32 = nullptr;
+    const int64_t *moff = nullptr;   // complex offset of the system's M^{-1} (shared by identical systems)
+    const void *m64 = nullptr, *m32 = nullptr;  // M^{-1}, complex column-major
+};
+void launch_full_unit(const FullDesc &F, int ns, const int32_t *mask, const int64_t *off, int k, double val,
+                      double *x, hipStream_t st);
+void launch_full_gather(const FullDesc &F, int ns, const int32_t *mask, const int64_t *off, int k,
+                        const double *z, const int64_t *soff, double *S, hipStream_t st);
+void launch_full_block(int r, const double *S, const int32_t *cptr, const int32_t *ccol, const double *cval,
+                       double *Bm, hipStream_t st);
+void launch_full_extract(int r, const double *Inv, double *M64, float *M32, hipStream_t st);
+// w[Gamma] = M^{-1} ((+-i) C_G z_G) (w zero elsewhere); u, part: scratch
+template <class T>
+void launch_full_correct(const FullDesc &F, int ns, const int32_t *mask, const int64_t *off, int conj, const T *z,
+                         T *u, T *part, T *w, hipStream_t st);
+
 // Setup (FP64): condensation, dense block assembly, block LU with explicit inverses.
 void launch_condense(int ncells, int n_loc, int n_int, const double *Kel, const int32_t *cell_dofs,
                      const uint8_t *dir, double *kiinv, double *F, double *Kcond, int32_t *status,

@@ -128,7 +128,8 @@ template <class T>
 static hipGraphExec_t step_graph(Krylov &K, const KOps<T> &ops, const GmresParams &p, hipStream_t st) {
     const int key = TypeKey<T>::v * 2 + (ops.csign < 0 ? 1 : 0);
     Krylov::GraphSlot &s = K.slots[key];
-    if (s.exec && s.owner == ops.owner && s.orth == p.orth && s.max_iter == p.max_iter && s.cplx == p.cplx)
+    if (s.exec && s.owner == ops.owner && s.orth == p.orth && s.max_iter == p.max_iter && s.cplx == p.cplx &&
+        s.pkind == ops.pkind)
         return s.exec;
     if (s.exec) (void)hipGraphExecDestroy(s.exec);
     if (s.graph) (void)hipGraphDestroy(s.graph);
@@ -149,6 +150,7 @@ static hipGraphExec_t step_graph(Krylov &K, const KOps<T> &ops, const GmresParam
     s.rtol = p.rtol;
     s.max_iter = p.max_iter;
     s.cplx = p.cplx;
+    s.pkind = ops.pkind;
     s.csign = ops.csign;
     s.key_T = TypeKey<T>::v;
     return s.exec;
@@ -461,24 +463,199 @@ void Ctx::build_prec() {
     prec_ready = true;
 }
 
-KOps<double> Ctx::ops64(float csign, bool with_prec) {
+// Boundary set Gamma (rows of the Dirichlet-modified C with a nonzero entry), C_G, and
+// M^{-1} = (I + i C_G S_G)^{-1} with S_G = P K^{-1} P^T, once per distinct system
+// (same factor, same Gamma, same C_G).
+void Ctx::build_full() {
+    if (full.ready) return;
+    build_prec();
+    const double t0 = now_ms();
+    std::vector<int64_t> goff(ns + 1, 0);
+    std::vector<int32_t> gam, cptr(1, 0), ccol;
+    std::vector<double> cval;
+    full.r.assign(ns, 0);
+    for (int s = 0; s < ns; ++s) {
+        thm_system &S = *sys[s];
+        const int64_t nnzc = (int64_t)S.C.col.size();
+        std::vector<double> hv(nnzc);
+        if (nnzc) THM_HIP(hipMemcpy(hv.data(), S.cval.p, sizeof(double) * nnzc, hipMemcpyDeviceToHost));
+        std::vector<int32_t> loc(S.n, -1), rows;
+        for (int64_t i = 0; i < S.n; ++i) {
+            if (S.dir[i]) continue;
+            bool any = false;
+            for (int32_t e = S.C.rowptr[i]; e < S.C.rowptr[i + 1]; ++e) any = any || hv[e] != 0.0;
+            if (any) {
+                loc[i] = (int32_t)rows.size();
+                rows.push_back((int32_t)i);
+            }
+        }
+        for (int32_t i : rows) {
+            gam.push_back(i);
+            for (int32_t e = S.C.rowptr[i]; e < S.C.rowptr[i + 1]; ++e) {
+                if (hv[e] == 0.0) continue;
+                const int32_t c = loc[S.C.col[e]];
+                if (c < 0) fail(THM_EUNSUPPORTED, "C couples a boundary DoF to a DoF outside the boundary set");
+                ccol.push_back(c);
+                cval.push_back(hv[e]);
+            }
+            cptr.push_back((int32_t)ccol.size());
+        }
+        full.r[s] = (int64_t)rows.size();
+        goff[s + 1] = goff[s] + full.r[s];
+    }
+    // representatives: the first system of each (factor, Gamma, C_G) class
+    std::vector<int> rep(ns);
+    auto same = [&](int a, int b) {
+        if (sys[a]->fac != sys[b]->fac || full.r[a] != full.r[b]) return false;
+        const int64_t ga = goff[a], gb = goff[b], r = full.r[a];
+        if (!std::equal(gam.begin() + ga, gam.begin() + ga + r, gam.begin() + gb)) return false;
+        if (cptr[ga + r] - cptr[ga] != cptr[gb + r] - cptr[gb]) return false;
+        for (int64_t i = 0; i <= r; ++i)
+            if (cptr[ga + i] - cptr[ga] != cptr[gb + i] - cptr[gb]) return false;
+        const int32_t ea = cptr[ga], eb = cptr[gb], ne = cptr[ga + r] - ea;
+        return std::equal(ccol.begin() + ea, ccol.begin() + ea + ne, ccol.begin() + eb) &&
+               std::equal(cval.begin() + ea, cval.begin() + ea + ne, cval.begin() + eb);
+    };
+    std::vector<int64_t> moff(ns, 0), soff(ns, 0);
+    std::vector<int32_t> isrep(ns, 0);
+    int64_t mtot = 0, maxr = 0, maxr_rep = 0;
+    full.nunique = 0;
+    for (int s = 0; s < ns; ++s) {
+        rep[s] = s;
+        for (int t = 0; t < s; ++t)
+            if (rep[t] == t && same(s, t)) {
+                rep[s] = t;
+                break;
+            }
+        maxr = std::max(maxr, full.r[s]);
+        if (rep[s] == s) {
+            moff[s] = mtot;
+            soff[s] = mtot;  // S_G (real) uses the same element offsets in its own buffer
+            mtot += full.r[s] * full.r[s];
+            isrep[s] = full.r[s] > 0;
+            maxr_rep = std::max(maxr_rep, full.r[s]);
+            ++full.nunique;
+        } else {
+            moff[s] = moff[rep[s]];
+        }
+    }
+    if (maxr > INT32_MAX / 4) fail(THM_EUNSUPPORTED, "boundary set too large for the complete inverse");
+    std::vector<float> cval32(cval.begin(), cval.end());
+    full.goff.upload(goff, st);
+    full.gam.upload(gam.empty() ? std::vector<int32_t>{0} : gam, st);
+    full.cptr.upload(cptr, st);
+    full.ccol.upload(ccol.empty() ? std::vector<int32_t>{0} : ccol, st);
+    full.cval64.upload(cval.empty() ? std::vector<double>{0.0} : cval, st);
+    full.cval32.upload(cval32.empty() ? std::vector<float>{0.f} : cval32, st);
+    full.moff.upload(moff, st);
+    full.m64.alloc(std::max<int64_t>(2 * mtot, 1));
+    full.m32.alloc(std::max<int64_t>(2 * mtot, 1));
+    FullDesc &d = full.d;
+    d.maxr = (int)maxr;
+    d.nchmax = (int)((maxr + 63) / 64);
+    d.goff = full.goff.p;
+    d.gam = full.gam.p;
+    d.cptr = full.cptr.p;
+    d.ccol = full.ccol.p;
+    d.cval64 = full.cval64.p;
+    d.cval32 = full.cval32.p;
+    d.moff = full.moff.p;
+    d.m64 = full.m64.p;
+    d.m32 = full.m32.p;
+    if (maxr_rep > 0) {
+        // S_G: columns 2k, 2k + 1 of every representative from one batched FP64 application
+        DBuf<double> Sg(std::max<int64_t>(mtot, 1)), xin(K.B.Ltot), zout(K.B.Ltot);
+        DBuf<int64_t> dsoff;
+        dsoff.upload(soff, st);
+        DBuf<int32_t> dmask;
+        dmask.upload(isrep, st);
+        THM_HIP(hipMemsetAsync(xin.p, 0, sizeof(double) * xin.n, st));
+        for (int64_t k = 0; 2 * k < maxr_rep; ++k) {
+            launch_full_unit(d, ns, dmask.p, K.B.off.p, (int)k, 1.0, xin.p, st);
+            launch_prec_apply<double>(P, P.d64.p, K.B.off.p, ns, dmask.p, xin.p, zout.p, ws64.p, ys64.p, tw64.p, st);
+            launch_full_gather(d, ns, dmask.p, K.B.off.p, (int)k, zout.p, dsoff.p, Sg.p, st);
+            launch_full_unit(d, ns, dmask.p, K.B.off.p, (int)k, 0.0, xin.p, st);
+        }
+        // M = I + i C_G S_G in real form, inverted by Gauss-Jordan, then stored complex
+        std::vector<int> reps;
+        int64_t btot = 0;
+        for (int s = 0; s < ns; ++s)
+            if (isrep[s]) {
+                reps.push_back(s);
+                btot += 4 * full.r[s] * full.r[s];
+            }
+        DBuf<double> Bm(btot), Inv(btot), Wk(btot);
+        DBuf<int32_t> piv(std::max<int64_t>(4 * maxr_rep * (int64_t)reps.size(), 1)), status(1);
+        THM_HIP(hipMemsetAsync(status.p, 0, sizeof(int32_t), st));
+        std::vector<InvDesc> jobs;
+        int64_t bo = 0;
+        for (size_t q = 0; q < reps.size(); ++q) {
+            const int s = reps[q];
+            const int r = (int)full.r[s];
+            launch_full_block(r, Sg.p + soff[s], full.cptr.p + goff[s], full.ccol.p, full.cval64.p, Bm.p + bo, st);
+            jobs.push_back({2 * r, Bm.p + bo, Wk.p + bo, Inv.p + bo, piv.p + 4 * maxr_rep * (int64_t)q, 2 * r});
+            bo += 4 * (int64_t)r * r;
+        }
+        DBuf<InvDesc> iscr;
+        launch_invert_batched(jobs, status.p, st, iscr);
+        int32_t hs = 0;
+        THM_HIP(hipMemcpyAsync(&hs, status.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        THM_HIP(hipStreamSynchronize(st));
+        if (hs) fail(THM_ESINGULAR, "I + i C_G S_G is singular");
+        bo = 0;
+        for (int s : reps) {
+            const int r = (int)full.r[s];
+            launch_full_extract(r, Inv.p + bo, full.m64.p + 2 * moff[s], full.m32.p + 2 * moff[s], st);
+            bo += 4 * (int64_t)r * r;
+        }
+        THM_HIP(hipStreamSynchronize(st));
+    }
+    const int64_t gt = std::max<int64_t>(goff[ns], 1);
+    full.u64.alloc(2 * gt);
+    full.u32.alloc(2 * gt);
+    full.part64.alloc(2 * gt * std::max(d.nchmax, 1));
+    full.part32.alloc(2 * gt * std::max(d.nchmax, 1));
+    full.w64.alloc(K.B.Ltot);
+    full.y64.alloc(K.B.Ltot);
+    full.w32.alloc(K.B.Ltot);
+    full.y32.alloc(K.B.Ltot);
+    THM_HIP(hipMemsetAsync(full.w64.p, 0, sizeof(double) * full.w64.n, st));
+    THM_HIP(hipMemsetAsync(full.w32.p, 0, sizeof(float) * full.w32.n, st));
+    full.neg1.upload(std::vector<double>(ns, -1.0), st);
+    full.bytes = mtot * (16 + 8);
+    THM_HIP(hipStreamSynchronize(st));
+    full.setup_ms = now_ms() - t0;
+    full.ready = true;
+}
+
+KOps<double> Ctx::ops64(float csign, bool with_prec, int pkind) {
     if (with_prec) build_prec();
+    if (with_prec && pkind == 1) build_full();
     KOps<double> o;
     o.apply = [this, csign](const double *x, double *y, const double *b, const int32_t *mask) {
         const Sched &sc = K.B.spmv_sched(lpr64, st);
         launch_spmv<double>(lpr64, mat64.p, K.B.off.p, sc, ns, mask, x, y, b, csign, st);
     };
-    o.prec = [this](const double *x, double *y, const int32_t *mask) {
+    o.prec = [this, csign, pkind](const double *x, double *y, const int32_t *mask) {
         if (!prec_ready) fail(THM_EINVAL, "preconditioner used before it was built");
         launch_prec_apply<double>(P, P.d64.p, K.B.off.p, ns, mask, x, y, ws64.p, ys64.p, tw64.p, st);
+        if (pkind == 1) {
+            // y -= K^{-1} P^T M^{-1} (+-i C_G y_G)
+            launch_full_correct<double>(full.d, ns, mask, K.B.off.p, csign < 0 ? 1 : 0, y, full.u64.p,
+                                        full.part64.p, full.w64.p, st);
+            launch_prec_apply<double>(P, P.d64.p, K.B.off.p, ns, mask, full.w64.p, full.y64.p, ws64.p, ys64.p,
+                                      tw64.p, st);
+            launch_axpy<double, double>(K.B, mask, full.neg1.p, full.y64.p, y, st);
+        }
     };
     o.graphable = true;
     o.owner = this;
     o.csign = csign;
+    o.pkind = pkind;
     return o;
 }
 
-KOps<float> Ctx::ops32(float csign, bool with_prec) {
+KOps<float> Ctx::ops32(float csign, bool with_prec, int pkind) {
     if (!x32.n) {
         x32.alloc(K.B.Ltot);
         b32.alloc(K.B.Ltot);
@@ -500,13 +677,22 @@ KOps<float> Ctx::ops32(float csign, bool with_prec) {
         const Sched &sc = K.B.spmv_sched(lpr32, st);
         launch_spmv<float>(lpr32, mat32.p, K.B.off.p, sc, ns, mask, x, y, b, csign, st);
     };
-    o.prec = [this](const float *x, float *y, const int32_t *mask) {
+    if (with_prec && pkind == 1) build_full();
+    o.prec = [this, csign, pkind](const float *x, float *y, const int32_t *mask) {
         if (!ws32.n) fail(THM_EINVAL, "preconditioner used before it was built");
         launch_prec_apply<float>(P, P.d32.p, K.B.off.p, ns, mask, x, y, ws32.p, ys32.p, tw32.p, st);
+        if (pkind == 1) {
+            launch_full_correct<float>(full.d, ns, mask, K.B.off.p, csign < 0 ? 1 : 0, y, full.u32.p,
+                                       full.part32.p, full.w32.p, st);
+            launch_prec_apply<float>(P, P.d32.p, K.B.off.p, ns, mask, full.w32.p, full.y32.p, ws32.p, ys32.p,
+                                     tw32.p, st);
+            launch_axpy<float, float>(K.B, mask, full.neg1.p, full.y32.p, y, st);
+        }
     };
     o.graphable = true;
     o.owner = this;
     o.csign = csign;
+    o.pkind = pkind;
     return o;
 }
 
@@ -525,8 +711,9 @@ void Ctx::solve(const thm_solve_opts &o, float csign, const int32_t *mask, std::
     gp.orth = o.orth;
     gp.use_graph = o.use_graph != 0;
     gp.cplx = o.krylov == THM_KRYLOV_COMPLEX ? 1 : 0;
+    const int pk = o.precond == THM_PREC_FULL ? 1 : 0;
     if (o.precision == THM_FP64) {
-        gmres_run<double>(K, ops64(csign), b64.p, x64.p, mask, gp, st);
+        gmres_run<double>(K, ops64(csign, true, pk), b64.p, x64.p, mask, gp, st);
         THM_HIP(hipMemcpyAsync(hi.data(), K.iters.p, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, st));
         THM_HIP(hipMemcpyAsync(hr.data(), K.resid.p, sizeof(double) * ns, hipMemcpyDeviceToHost, st));
         THM_HIP(hipStreamSynchronize(st));
@@ -537,8 +724,8 @@ void Ctx::solve(const thm_solve_opts &o, float csign, const int32_t *mask, std::
         return;
     }
     // FP32 inner GMRES inside FP64 iterative refinement
-    KOps<double> A64 = ops64(csign);
-    KOps<float> A32 = ops32(csign);
+    KOps<double> A64 = ops64(csign, true, pk);
+    KOps<float> A32 = ops32(csign, true, pk);
     launch_norm2<double>(K.B, mask, b64.p, K.part.p, st);
     launch_norm_finish(K.B, K.part.p, mask, bnorm64.p, nullptr, 0.0, nullptr, nullptr, st);
     THM_HIP(hipMemcpyAsync(run_ir.p, mask, sizeof(int32_t) * ns, hipMemcpyDeviceToDevice, st));

@@ -108,7 +108,7 @@ struct Krylov {
     struct GraphSlot {
         hipGraphExec_t exec = nullptr;
         hipGraph_t graph = nullptr;
-        int key_T = -1, orth = -1, max_iter = -1, cplx = -1;
+        int key_T = -1, orth = -1, max_iter = -1, cplx = -1, pkind = -1;
         float csign = 0.f;
         double rtol = -1.0;
         const void *owner = nullptr;
@@ -132,6 +132,7 @@ struct KOps {
     bool graphable = false;
     const void *owner = nullptr;  // identity of the operator (graph cache key)
     float csign = 1.f;
+    int pkind = 0;                // preconditioner: 0 block diag(K, K)^{-1}, 1 complete (K +- iC)^{-1}
 };
 
 struct GmresParams {
@@ -166,11 +167,27 @@ struct Ctx {
 
     bool prec_ready = false;
 
+    // complete inverse (K + iC)^{-1} = K^{-1} - K^{-1} P^T M^{-1} (i C_G P) K^{-1} (see kernels_full.hip)
+    struct Full {
+        bool ready = false;
+        FullDesc d;
+        std::vector<int64_t> r;                     // boundary size per system
+        int nunique = 0;                            // distinct M^{-1} stored
+        DBuf<int64_t> goff, moff;
+        DBuf<int32_t> gam, cptr, ccol;
+        DBuf<double> cval64, m64, u64, part64, w64, y64, neg1;
+        DBuf<float> cval32, m32, u32, part32, w32, y32;
+        int64_t bytes = 0;                          // M^{-1} storage, FP64 + FP32
+        double setup_ms = 0.0;
+    } full;
+    void build_full();
+
     void build(const std::vector<thm_system *> &s, int m, hipStream_t stream);
     void build_prec();
-    // operator (and, unless with_prec is false, preconditioner) of the batch
-    KOps<double> ops64(float csign, bool with_prec = true);
-    KOps<float> ops32(float csign, bool with_prec = true);
+    // operator (and, unless with_prec is false, preconditioner) of the batch; pkind selects
+    // the block preconditioner (0) or the complete inverse (1)
+    KOps<double> ops64(float csign, bool with_prec = true, int pkind = 0);
+    KOps<float> ops32(float csign, bool with_prec = true, int pkind = 0);
     // Solve A x = b for the systems in mask (device, nullable = all); b64/x64 slots hold
     // the right-hand sides and initial guesses (zero on Dirichlet rows).
     void solve(const thm_solve_opts &o, float csign, const int32_t *mask, std::vector<int> &iters,

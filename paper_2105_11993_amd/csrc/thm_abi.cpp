@@ -848,6 +848,12 @@ static void ddm_solve_impl(thm_system &G, const thm_solve_opts &o, double *E, th
     stt.outer_iters = outer;
     stt.refinements = 0;
     stt.fp64_fallback = run.fallbacks;
+    stt.precond_extra_bytes = 0;
+    if (o.precond == THM_PREC_FULL) {
+        if (batched) stt.precond_extra_bytes = D.inner ? D.inner->full.bytes : 0;
+        else
+            for (auto &c : D.singles) stt.precond_extra_bytes += c->full.bytes;
+    }
     stt.rel_residual = res;
     stt.setup_ms = setup + (t1 - t0);
     stt.solve_ms = now_ms() - t1;
@@ -874,6 +880,7 @@ void thm_default_opts(thm_solve_opts *o) {
     o->ir_inner_rtol = 1e-6;
     o->max_refine = 30;
     o->krylov = THM_KRYLOV_COMPLEX;
+    o->precond = THM_PREC_BLOCK;
 }
 
 const char *thm_last_error(void) { return g_last_error.c_str(); }
@@ -886,6 +893,7 @@ static void check_opts(const thm_solve_opts *o) {
     if (o->precision != THM_FP64 && o->precision != THM_FP32_IR) fail(THM_EINVAL, "unknown precision");
     if (o->orth != THM_ORTH_CGS && o->orth != THM_ORTH_CGS2) fail(THM_EINVAL, "unknown orthogonalisation");
     if (o->krylov != THM_KRYLOV_COMPLEX && o->krylov != THM_KRYLOV_REAL) fail(THM_EINVAL, "unknown krylov kind");
+    if (o->precond != THM_PREC_BLOCK && o->precond != THM_PREC_FULL) fail(THM_EINVAL, "unknown preconditioner");
 }
 
 thm_status thm_assemble(const thm_problem *p, void *stream, thm_system **out) {
@@ -948,6 +956,7 @@ thm_status thm_gmres_solve(int32_t nsys, thm_system *const *sys, const thm_solve
                 o.outer_iters = 0;
                 o.refinements = rf[s];
                 o.fp64_fallback = c.last_fb[s];
+                o.precond_extra_bytes = opts->precond == THM_PREC_FULL ? c.full.bytes : 0;
                 o.rel_residual = rs[s];
                 o.status = (rs[s] <= opts->rtol) ? THM_OK : THM_NOT_CONVERGED;
                 o.setup_ms = (grp[s]->fac ? grp[s]->fac->setup_ms : 0.0) + (t1 - t0);
@@ -1104,6 +1113,29 @@ thm_status thm_apply_precond(thm_system *sys, int32_t precision, const void *x_d
             launch_scale<float, double>(c.K.B, nullptr, nullptr, 0, c.b32.p, c.r64.p, nullptr, 0, nullptr, c.st);
         } else {
             c.ops64(1.f).prec(c.x64.p, c.r64.p, nullptr);
+        }
+        c.copy_out(0, c.r64.p, (double *)y_dev);
+        stream_join(c.st, us);
+        THM_HIP(hipStreamSynchronize(us));
+    });
+}
+
+thm_status thm_apply_precond_full(thm_system *sys, int32_t transpose, int32_t precision, const void *x_dev,
+                                  void *y_dev, void *stream) {
+    return guard([&] {
+        if (!sys || !x_dev || !y_dev) fail(THM_EINVAL, "bad arguments");
+        hipStream_t us = (hipStream_t)stream;
+        Ctx &c = get_ctx({sys}, 50);
+        stream_join(us, c.st);
+        c.copy_in(0, (const double *)x_dev, c.x64.p);
+        const float cs = transpose ? -1.f : 1.f;
+        if (precision == THM_FP32_IR) {
+            KOps<float> o = c.ops32(cs, true, 1);
+            launch_scale<double, float>(c.K.B, nullptr, nullptr, 0, c.x64.p, c.x32.p, nullptr, 0, nullptr, c.st);
+            o.prec(c.x32.p, c.b32.p, nullptr);
+            launch_scale<float, double>(c.K.B, nullptr, nullptr, 0, c.b32.p, c.r64.p, nullptr, 0, nullptr, c.st);
+        } else {
+            c.ops64(cs, true, 1).prec(c.x64.p, c.r64.p, nullptr);
         }
         c.copy_out(0, c.r64.p, (double *)y_dev);
         stream_join(c.st, us);
