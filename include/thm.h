@@ -60,7 +60,8 @@ typedef enum { THM_KRYLOV_COMPLEX = 0, THM_KRYLOV_REAL = 1 } thm_krylov;
  * (K - iC)^{-1}) applied exactly as z - K^{-1} P^T M^{-1} (i C_G P z), z = K^{-1} b, where P
  * restricts to the boundary DoFs Gamma that carry C, C_G is C on Gamma and
  * M = I + i C_G P K^{-1} P^T (r x r complex, r = |Gamma|; stored once per distinct system).
- * One application costs two applications of K^{-1} plus an r x r complex product. */
+ * One application costs two applications of K^{-1} plus an r x r complex product.  Use it
+ * with THM_FP64: in FP32 the correction cancels and refinement needs many inner steps. */
 typedef enum { THM_PREC_BLOCK = 0, THM_PREC_FULL = 1 } thm_precond;
 
 /* Problem statement (paper Sec. 2, eq. (1); partition eq. (5)).  Copied by thm_assemble. */
