@@ -282,12 +282,13 @@ struct FeTables {
     int npts = 0;
     DBuf<double> pts, w;         // npts x 3, npts
     DBuf<double> val, curl;      // n_loc x 3 x npts
+    DBuf<double> ref;            // reference mass and curl-curl matrices of the cell (2 n_loc^2; set on first use)
 };
 void fe_gauss(int q, DBuf<double> &x, DBuf<double> &w, hipStream_t st);
 void fe_tables_cell(int dim, int p, int q, const LocalFn *fns_dev, int n_loc, FeTables &T, hipStream_t st);
 void fe_tables_side(int dim, int p, int q, int axis, int side, const LocalFn *fns_dev, int n_loc, FeTables &T,
                     hipStream_t st);
-void launch_element_matrices(int dim, int64_t ncells, int n_loc, const FeTables &T, const double *h,
+void launch_element_matrices(int dim, int64_t ncells, int n_loc, FeTables &T, const double *h,
                              const double *mu, double omega, double *Kel, hipStream_t st);
 void launch_gather(int64_t nnz, const int32_t *gptr, const int32_t *gsrc, const double *src, double scale,
                    double *val, hipStream_t st);

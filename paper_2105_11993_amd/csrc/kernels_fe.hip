@@ -178,17 +178,18 @@ void fe_tables_side(int dim, int p, int q, int, int, const LocalFn *fns, int n_l
     THM_HIP(hipStreamSynchronize(st));
 }
 
-// K_c[u][v] = mu_c^{-1} int curl phi_u . curl phi_v - w^2 int phi_u . phi_v   (eq. (3), K = A - w^2 M)
-__global__ void __launch_bounds__(256) k_element(int dim, int64_t ncells, int n_loc, int npts,
-                                                 const double *__restrict__ val, const double *__restrict__ curl,
-                                                 const double *__restrict__ w, const double *__restrict__ h,
-                                                 const double *__restrict__ mu, double omega,
-                                                 double *__restrict__ Kel) {
-    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Reference matrices of the cell: RM[u][v] = sum_r cm_r sum_q w_q f_u^r f_v^r over the value
+// components and RA[u][v] = sum_r cc_r sum_q w_q (curl f_u)^r (curl f_v)^r over the curl
+// components, where cm_r, cc_r are the covariant-Piola factors of the cell's edge lengths h.
+// On an axis-aligned box that map is diagonal, so every element matrix of eq. (3) is
+// K_c = RA / mu_c - w^2 RM (the same sums, in the same order, for every cell).
+__global__ void __launch_bounds__(256) k_ref_matrices(int dim, int n_loc, int npts, const double *__restrict__ val,
+                                                      const double *__restrict__ curl, const double *__restrict__ w,
+                                                      const double *__restrict__ h, double *__restrict__ R) {
     const int64_t nl2 = (int64_t)n_loc * n_loc;
-    if (id >= ncells * nl2) return;
-    const int64_t c = id / nl2;
-    const int u = (int)((id % nl2) / n_loc), v = (int)(id % n_loc);
+    const int64_t uv = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (uv >= nl2) return;
+    const int u = (int)(uv / n_loc), v = (int)(uv % n_loc);
     const double hx = h[0], hy = h[1], hz = dim == 3 ? h[2] : 1.0;
     const double det = hx * hy * hz;
     const double hh[3] = {hx, hy, hz};
@@ -211,15 +212,49 @@ __global__ void __launch_bounds__(256) k_element(int dim, int64_t ncells, int n_
         for (int q = 0; q < npts; ++q) s += w[q] * cu[q] * cv[q];
         a += cc[r] * s;
     }
-    const double muc = mu ? mu[c] : 1.0;
-    Kel[id] = a / muc - omega * omega * m;
+    R[uv] = m;
+    R[nl2 + uv] = a;
 }
 
-void launch_element_matrices(int dim, int64_t ncells, int n_loc, const FeTables &T, const double *h,
+// K_c[u][v] = mu_c^{-1} int curl phi_u . curl phi_v - w^2 int phi_u . phi_v   (eq. (3), K = A - w^2 M):
+// one pass over the output.  Block (x, y) owns entries [1024 x, 1024 x + 1024) of the
+// element matrix (four per thread, consecutive threads at consecutive addresses) and the
+// cells y, y + gridDim.y, ...; the reference entries stay in registers across its cells.
+__global__ void __launch_bounds__(256) k_element(int64_t ncells, int n_loc, const double *__restrict__ R,
+                                                 const double *__restrict__ mu, double omega,
+                                                 double *__restrict__ Kel) {
+    const int nl2 = n_loc * n_loc;
+    double rm[4], ra[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int uv = blockIdx.x * 1024 + k * 256 + threadIdx.x;
+        rm[k] = uv < nl2 ? R[uv] : 0.0;
+        ra[k] = uv < nl2 ? R[nl2 + uv] : 0.0;
+    }
+    const double w2 = omega * omega;
+    for (int64_t c = blockIdx.y; c < ncells; c += gridDim.y) {
+        const double inv = mu ? 1.0 / mu[c] : 1.0;
+        double *K = Kel + c * nl2;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int uv = blockIdx.x * 1024 + k * 256 + threadIdx.x;
+            if (uv < nl2) K[uv] = ra[k] * inv - w2 * rm[k];
+        }
+    }
+}
+
+void launch_element_matrices(int dim, int64_t ncells, int n_loc, FeTables &T, const double *h,
                              const double *mu, double omega, double *Kel, hipStream_t st) {
-    const int64_t tot = ncells * n_loc * n_loc;
-    k_element<<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(dim, ncells, n_loc, T.npts, T.val.p, T.curl.p, T.w.p,
-                                                             h, mu, omega, Kel);
+    const int64_t nl2 = (int64_t)n_loc * n_loc;
+    if ((int64_t)T.ref.n != 2 * nl2) {
+        T.ref.alloc(2 * nl2);
+        k_ref_matrices<<<(unsigned)((nl2 + 255) / 256), 256, 0, st>>>(dim, n_loc, T.npts, T.val.p, T.curl.p, T.w.p, h,
+                                                                      T.ref.p);
+    }
+    if (ncells > 0) {
+        const dim3 grid((unsigned)((nl2 + 1023) / 1024), (unsigned)std::min<int64_t>(ncells, 2048));
+        k_element<<<grid, 256, 0, st>>>(ncells, n_loc, T.ref.p, mu, omega, Kel);
+    }
     THM_HIP(hipGetLastError());
 }
 
