@@ -39,7 +39,7 @@ typedef enum {
     THM_OK = 0,
     THM_NOT_CONVERGED = 1,  /* best iterate written, stats filled */
     THM_EINVAL = -1,        /* null pointer, bad size, mu <= 0 or non-finite, w <= 0, no Gamma^inf */
-    THM_EUNSUPPORTED = -2,  /* dim not in {2,3}, degree > 3 (2D) / > 2 (3D), uneven partition */
+    THM_EUNSUPPORTED = -2,  /* dim not in {2,3}, degree > 3 (2D) / > 1 (3D), uneven partition */
     THM_ENOMEM = -3,        /* device allocation failed */
     THM_EHIP = -4,          /* HIP runtime error (message carries hipGetErrorString) */
     THM_ESINGULAR = -5      /* zero or non-finite pivot while factorising the preconditioner */
