@@ -58,6 +58,7 @@ class DDM:
         self.subs = []
         nsub = int(np.prod(S))
         mu_g = prob.mu_cells(gm.n_cells).reshape(tuple(reversed(n)))
+        eps_g = prob.eps_cells(gm.n_cells).reshape(tuple(reversed(n)))
         for s in range(nsub):
             pos = self.sub_pos(s)
             lo = [gm.lo[a] + pos[a] * nloc[a] * gm.h[a] for a in range(d)]
@@ -72,7 +73,7 @@ class DDM:
             mu_l = mu_g[sl].ravel()
             lp = replace(prob, n=tuple(nloc) + (1,) * (3 - d), lo=tuple(lo) + (0.0,) * (3 - d),
                          hi=tuple(hi) + (1.0,) * (3 - d), inc_faces=inc, mu=mu_l,
-                         subdomains=(1, 1, 1))
+                         eps=eps_g[sl].ravel(), subdomains=(1, 1, 1))
             ls = system.assemble(lp)
             # local -> global DoF map through the shared local cell ordering
             lm = ls.mesh

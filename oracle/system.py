@@ -8,6 +8,9 @@ matrix S = K + iC with
     K = A - w^2 M   (A: mu^{-1} curl-curl, M: mass; real symmetric, indefinite)
     C = k w M_inf   (tangential trace mass on Gamma^inf; real symmetric PSD).
 Readings of the paper used here:
+ * materials of refractive index n (the block benchmark of Sec. 4.1) enter as a relative
+   permittivity eps = n^2 per cell in the mass term, curl(mu^{-1} curl E) - w^2 eps E = 0,
+   so M is the eps-weighted mass (the paper's equations carry mu only; eps = 1 there);
  * the impedance coefficient is i k w without mu (the strong form's coefficient;
    integration by parts of eq. (1) gives exactly +i k w int g^T E . g^T phi);
  * B of eq. (4) is real (the i is factored out): S = K + iC <-> [[K, -C], [C, K]];
@@ -41,6 +44,7 @@ class Problem:
     lo: tuple = (0.0, 0.0, 0.0)
     hi: tuple = (1.0, 1.0, 1.0)
     subdomains: tuple = (1, 1, 1)
+    eps: np.ndarray = None           # relative permittivity per cell (refractive index squared); None -> 1
 
     def mesh(self):
         return BoxMesh(self.dim, self.n, self.lo, self.hi, self.p)
@@ -51,6 +55,13 @@ class Problem:
         mu = np.asarray(self.mu, dtype=np.float64).ravel()
         assert mu.size == n_cells
         return mu
+
+    def eps_cells(self, n_cells):
+        if self.eps is None:
+            return np.ones(n_cells)
+        eps = np.asarray(self.eps, dtype=np.float64).ravel()
+        assert eps.size == n_cells
+        return eps
 
     def einc(self):
         d = np.asarray(self.inc_dir[: self.dim], dtype=np.float64)
@@ -81,7 +92,7 @@ class System:
     Mhat: np.ndarray       # element mass (uniform box)
     Ahat: np.ndarray       # element unit-coefficient curl-curl
     K: sp.csr_matrix
-    M: sp.csr_matrix
+    M: sp.csr_matrix       # eps-weighted mass
     A: sp.csr_matrix
     Minf: sp.csr_matrix
     C: sp.csr_matrix
@@ -162,7 +173,8 @@ def assemble(prob, extra_inf_sides=()):
     mu = prob.mu_cells(mesh.n_cells)
     Mh, Ah = fe.element_matrices(mesh.dim, mesh.p, mesh.h)
     nc = mesh.n_cells
-    Mb = np.broadcast_to(Mh, (nc,) + Mh.shape)
+    # mass weighted by the cell's relative permittivity (K = A - w^2 M_eps; eps = 1 is eq. (3))
+    Mb = Mh[None, :, :] * prob.eps_cells(nc)[:, None, None]
     Ab = Ah[None, :, :] / mu[:, None, None]
     r, c, v = _coo(T, np.ascontiguousarray(Mb))
     M = sp.coo_matrix((v, (r, c)), shape=(N, N)).tocsr()

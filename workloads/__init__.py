@@ -17,6 +17,9 @@ E^inc = pol * exp(-i w d.x) on the x = 0 side, impedance on every other side):
   c5  2D 128^2 quads, degree 1, w = 30, mu = clip(1 + 3 f, 1, 4) with f a
       standardised Gaussian random field (seed 5, correlation length 0.1);
       target box [0.7,0.9]^2; 32 finite-difference cells (seed 6)
+  block  the block benchmark of Sec. 4.1: unit square, a centre square of refractive
+      index 1.516 (eps = 1.516^2) in air (eps = 1); centre [0.25, 0.75]^2 (the paper gives
+      no size), degree 1, mesh m^2, single domain, swept over w in {5, 10, 20, 40, 80}
 """
 import math
 
@@ -26,7 +29,7 @@ import numpy as np
 def _base(dim, n, p, omega, **kw):
     d = dict(dim=dim, n=tuple(n) + (1,) * (3 - len(n)), p=p, omega=float(omega), kappa=1.0,
              mu=None, inc_faces=1, inc_dir=(1.0, 0.0, 0.0), inc_pol=(0.0, 1.0, 0.0),
-             lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), subdomains=(1, 1, 1))
+             lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), subdomains=(1, 1, 1), eps=None)
     d.update(kw)
     return d
 
@@ -98,3 +101,19 @@ C5_TARGET = ((0.7, 0.7, 0.0), (0.9, 0.9, 1.0))
 
 def fd_cells(n_cells, count=32, seed=6):
     return np.sort(np.random.default_rng(seed).choice(n_cells, size=count, replace=False))
+
+
+BLOCK_OMEGAS = (5.0, 10.0, 20.0, 40.0, 80.0)
+
+
+def eps_block(m, n_center=1.516, lo=0.25, hi=0.75):
+    """eps per cell of an m x m unit square (x fastest): n_center^2 where the cell centre lies
+    in [lo, hi]^2, 1 elsewhere."""
+    c = (np.arange(m) + 0.5) / m
+    inside = (c >= lo) & (c <= hi)
+    e = np.where(inside[:, None] & inside[None, :], n_center ** 2, 1.0)  # [j, i]
+    return e.ravel()
+
+
+def block(m=128, omega=20.0, p=1):
+    return _base(2, (m, m), p, omega, eps=eps_block(m))
