@@ -79,6 +79,9 @@ typedef struct {
     double inc_pol_re[3];
     double inc_pol_im[3];
     int32_t subdomains[3];   /* box partition for thm_ddm_solve; {1,1,1} = single domain */
+    const double *eps;       /* host, n_cells relative permittivities > 0 (x fastest): a material of
+                                refractive index n (Sec. 4.1's block benchmark) has eps = n^2 and enters
+                                the mass term, K_c = mu_c^{-1} A_c - w^2 eps_c M_c; NULL -> 1 (eq. (3)) */
 } thm_problem;
 
 /* Solver options.  thm_default_opts fills the defaults listed here. */

@@ -31,7 +31,8 @@ class ThmProblem(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("cells", _i3), ("box_lo", _d3), ("box_hi", _d3),
                 ("degree", ctypes.c_int32), ("omega", ctypes.c_double), ("kappa", ctypes.c_double),
                 ("mu", ctypes.POINTER(ctypes.c_double)), ("inc_faces", ctypes.c_uint32), ("inc_dir", _d3),
-                ("inc_pol_re", _d3), ("inc_pol_im", _d3), ("subdomains", _i3)]
+                ("inc_pol_re", _d3), ("inc_pol_im", _d3), ("subdomains", _i3),
+                ("eps", ctypes.POINTER(ctypes.c_double))]
 
 
 class ThmSolveOpts(ctypes.Structure):
@@ -140,7 +141,7 @@ def default_opts(**kw):
 
 def make_problem(d):
     """ThmProblem from a workload dict (dim, n, p, omega, kappa, mu, inc_faces, inc_dir,
-    inc_pol, lo, hi, subdomains).  Returns (struct, keep-alive buffer)."""
+    inc_pol, lo, hi, subdomains, eps).  Returns (struct, keep-alive buffers)."""
     p = ThmProblem()
     dim = int(d["dim"])
     p.dim = dim
@@ -153,11 +154,13 @@ def make_problem(d):
     p.degree = int(d["p"])
     p.omega = float(d["omega"])
     p.kappa = float(d.get("kappa", 1.0))
-    keep = None
-    mu = d.get("mu")
-    if mu is not None:
-        keep = np.ascontiguousarray(np.asarray(mu, dtype=np.float64).ravel())
-        p.mu = keep.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    keep = []
+    for name in ("mu", "eps"):
+        v = d.get(name)
+        if v is not None:
+            arr = np.ascontiguousarray(np.asarray(v, dtype=np.float64).ravel())
+            keep.append(arr)
+            setattr(p, name, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     p.inc_faces = int(d.get("inc_faces", 1))
     dirv = list(d.get("inc_dir", (1.0, 0.0, 0.0))) + [0.0] * 3
     pol = [complex(v) for v in list(d.get("inc_pol", (0.0, 1.0, 0.0))) + [0.0] * 3]

@@ -289,7 +289,7 @@ void fe_tables_cell(int dim, int p, int q, const LocalFn *fns_dev, int n_loc, Fe
 void fe_tables_side(int dim, int p, int q, int axis, int side, const LocalFn *fns_dev, int n_loc, FeTables &T,
                     hipStream_t st);
 void launch_element_matrices(int dim, int64_t ncells, int n_loc, FeTables &T, const double *h,
-                             const double *mu, double omega, double *Kel, hipStream_t st);
+                             const double *mu, const double *eps, double omega, double *Kel, hipStream_t st);
 void launch_gather(int64_t nnz, const int32_t *gptr, const int32_t *gsrc, const double *src, double scale,
                    double *val, hipStream_t st);
 void launch_side_mass(int dim, int nsides, const int32_t *side_axis, const int32_t *side_side,

@@ -221,8 +221,8 @@ __global__ void __launch_bounds__(256) k_ref_matrices(int dim, int n_loc, int np
 // element matrix (four per thread, consecutive threads at consecutive addresses) and the
 // cells y, y + gridDim.y, ...; the reference entries stay in registers across its cells.
 __global__ void __launch_bounds__(256) k_element(int64_t ncells, int n_loc, const double *__restrict__ R,
-                                                 const double *__restrict__ mu, double omega,
-                                                 double *__restrict__ Kel) {
+                                                 const double *__restrict__ mu, const double *__restrict__ eps,
+                                                 double omega, double *__restrict__ Kel) {
     const int nl2 = n_loc * n_loc;
     double rm[4], ra[4];
 #pragma unroll
@@ -234,17 +234,18 @@ __global__ void __launch_bounds__(256) k_element(int64_t ncells, int n_loc, cons
     const double w2 = omega * omega;
     for (int64_t c = blockIdx.y; c < ncells; c += gridDim.y) {
         const double inv = mu ? 1.0 / mu[c] : 1.0;
+        const double we = eps ? w2 * eps[c] : w2;  // relative permittivity weights the mass
         double *K = Kel + c * nl2;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int uv = blockIdx.x * 1024 + k * 256 + threadIdx.x;
-            if (uv < nl2) K[uv] = ra[k] * inv - w2 * rm[k];
+            if (uv < nl2) K[uv] = ra[k] * inv - we * rm[k];
         }
     }
 }
 
 void launch_element_matrices(int dim, int64_t ncells, int n_loc, FeTables &T, const double *h,
-                             const double *mu, double omega, double *Kel, hipStream_t st) {
+                             const double *mu, const double *eps, double omega, double *Kel, hipStream_t st) {
     const int64_t nl2 = (int64_t)n_loc * n_loc;
     if ((int64_t)T.ref.n != 2 * nl2) {
         T.ref.alloc(2 * nl2);
@@ -253,7 +254,7 @@ void launch_element_matrices(int dim, int64_t ncells, int n_loc, FeTables &T, co
     }
     if (ncells > 0) {
         const dim3 grid((unsigned)((nl2 + 1023) / 1024), (unsigned)std::min<int64_t>(ncells, 2048));
-        k_element<<<grid, 256, 0, st>>>(ncells, n_loc, T.ref.p, mu, omega, Kel);
+        k_element<<<grid, 256, 0, st>>>(ncells, n_loc, T.ref.p, mu, eps, omega, Kel);
     }
     THM_HIP(hipGetLastError());
 }

@@ -53,6 +53,7 @@ struct Factor {
 struct thm_system {
     thm_problem prob{};
     std::vector<double> mu_host;
+    std::vector<double> eps_host;  // empty: eps = 1
     uint32_t iface_sides = 0;  // sides that are DDM interfaces (impedance with k w)
     thm::Topo topo;
     thm::HostCSR K, C, Minc;
@@ -68,7 +69,7 @@ struct thm_system {
     thm::DBuf<int32_t> side_fn, sc_axis, sc_side, sc_cell, si_axis, si_side, si_cell;
     thm::DBuf<double> h, lo;
     thm::DBuf<int32_t> ncell;
-    thm::DBuf<double> mu_d;
+    thm::DBuf<double> mu_d, eps_d;
     thm::DBuf<double> kel, kraw, kval, craw, cval;
     thm::DBuf<float> kval32, cval32;
     thm::DBuf<int32_t> sl_ptr, sl_col, sl_src, sl_row;  // K in SELL-64 (see MatDesc)

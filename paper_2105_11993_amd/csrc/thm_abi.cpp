@@ -150,6 +150,9 @@ static void validate(const thm_problem *p) {
     if (p->mu)
         for (int64_t c = 0; c < nc; ++c)
             if (!(p->mu[c] > 0.0) || !std::isfinite(p->mu[c])) fail(THM_EINVAL, "mu must be finite and > 0");
+    if (p->eps)
+        for (int64_t c = 0; c < nc; ++c)
+            if (!(p->eps[c] > 0.0) || !std::isfinite(p->eps[c])) fail(THM_EINVAL, "eps must be finite and > 0");
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(p->inc_dir[a]) || !std::isfinite(p->inc_pol_re[a]) || !std::isfinite(p->inc_pol_im[a]))
             fail(THM_EINVAL, "incident field parameters must be finite");
@@ -248,7 +251,8 @@ static void compute_lift(thm_system &S, hipStream_t st) {
 // K values from the current mu: element kernel, gather, Dirichlet rows/columns, FP32 copy.
 static void assemble_K(thm_system &S, hipStream_t st) {
     const Topo &t = S.topo;
-    launch_element_matrices(t.dim, t.n_cells, t.n_loc, S.tcell, S.h.p, S.mu_d.p, S.prob.omega, S.kel.p, st);
+    launch_element_matrices(t.dim, t.n_cells, t.n_loc, S.tcell, S.h.p, S.mu_d.p, S.eps_d.n ? S.eps_d.p : nullptr,
+                            S.prob.omega, S.kel.p, st);
     const int64_t nnz = (int64_t)S.K.col.size();
     launch_gather(nnz, S.k_gptr.p, S.k_gsrc.p, S.kel.p, 1.0, S.kraw.p, st);
     THM_HIP(hipMemcpyAsync(S.kval.p, S.kraw.p, sizeof(double) * nnz, hipMemcpyDeviceToDevice, st));
@@ -260,6 +264,7 @@ static void assemble_K(thm_system &S, hipStream_t st) {
 static void assemble_system(thm_system &S, const thm_problem &p, uint32_t iface_sides, hipStream_t st) {
     S.prob = p;
     S.prob.mu = nullptr;
+    S.prob.eps = nullptr;
     S.iface_sides = iface_sides;
     Topo &t = S.topo;
     t.build(p.dim, p.degree, p.cells, p.box_lo, p.box_hi);
@@ -267,6 +272,8 @@ static void assemble_system(thm_system &S, const thm_problem &p, uint32_t iface_
     const int nl = t.n_loc;
     S.mu_host.assign(t.n_cells, 1.0);
     if (p.mu) std::copy(p.mu, p.mu + t.n_cells, S.mu_host.begin());
+    S.eps_host.clear();
+    if (p.eps) S.eps_host.assign(p.eps, p.eps + t.n_cells);
     S.sides_c.clear();
     S.sides_inc.clear();
     for (int axis = 0; axis < t.dim; ++axis)
@@ -344,6 +351,8 @@ static void assemble_system(thm_system &S, const thm_problem &p, uint32_t iface_
     S.lo.upload(std::vector<double>(t.lo, t.lo + 3), st);
     S.ncell.upload(std::vector<int32_t>(t.n, t.n + 3), st);
     S.mu_d.upload(S.mu_host, st);
+    if (!S.eps_host.empty()) S.eps_d.upload(S.eps_host, st);
+    else S.eps_d.release();
     S.dir_d.upload(S.dir, st);
     // reference tables: cell Gauss q = p+2, side Gauss q = p+2, incident load 10 points per direction
     fe_tables_cell(t.dim, t.p, t.p + 2, S.fns.p, nl, S.tcell, st);
@@ -429,14 +438,17 @@ static void build_ddm(thm_system &G, hipStream_t st) {
             else iface |= 1u << (2 * a + 1);
         }
         lp.inc_faces = inc;
-        std::vector<double> mu_l((size_t)nloc[0] * nloc[1] * nloc[2]);
+        std::vector<double> mu_l((size_t)nloc[0] * nloc[1] * nloc[2]), eps_l;
+        if (!G.eps_host.empty()) eps_l.resize(mu_l.size());
         for (size_t c = 0; c < mu_l.size(); ++c) {
             const int i = (int)(c % nloc[0]), j = (int)((c / nloc[0]) % nloc[1]), k = (int)(c / ((size_t)nloc[0] * nloc[1]));
             const int64_t gc = ((int64_t)(k + pos[2] * nloc[2]) * p.cells[1] + (j + pos[1] * nloc[1])) * p.cells[0] +
                                (i + pos[0] * nloc[0]);
             mu_l[c] = G.mu_host[gc];
+            if (!eps_l.empty()) eps_l[c] = G.eps_host[gc];
         }
         lp.mu = mu_l.data();
+        lp.eps = eps_l.empty() ? nullptr : eps_l.data();
         auto sub = std::make_unique<thm_system>();
         assemble_system(*sub, lp, iface, st);
         const Topo &lt = sub->topo;
