@@ -29,9 +29,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["c2", "c3", "c4"], default="c2",
-                    help="c2 (default, the benchmark line); c3: 3D DDM; c4: batch of uneven independent problems")
-    ap.add_argument("--mesh", type=int, default=None, help="cells per side (c2: 256, c3: 32)")
+    ap.add_argument("--workload", choices=["c2", "c3", "c4", "block"], default="c2",
+                    help="c2 (default, the benchmark line); c3: 3D DDM; c4: batch of uneven independent problems; "
+                         "block: the block benchmark's w sweep (refractive index 1.516 centre square)")
+    ap.add_argument("--mesh", type=int, default=None, help="cells per side (c2: 256, c3: 32, block: 128)")
     ap.add_argument("--count", type=int, default=256, help="c4: number of problems")
     ap.add_argument("--scale", type=int, default=1, help="c4: divide every mesh size by this")
     ap.add_argument("--skip-plain", action="store_true")
@@ -237,6 +238,37 @@ def run_batch(args, thm, torch, workloads):
     print(json.dumps(out))
 
 
+def run_block_sweep(args, thm, torch, workloads):
+    """The block benchmark of Sec. 4.1 (unit square, centre square [0.25, 0.75]^2 of refractive
+    index 1.516, eps = n^2, in air; degree 1, single domain): GMRES(50) iterations and time to
+    1e-8 for each w in {5, 10, 20, 40, 80} with the block preconditioner (FP64 and FP32 +
+    refinement) and with the complete inverse (FP64).  One JSON line."""
+    m = args.mesh or 128
+    rows = []
+    for w in workloads.BLOCK_OMEGAS:
+        S = thm.thm_assemble(workloads.block(m=m, omega=w))
+        row = {"omega": w, "n_dofs": S.info["n_dofs"]}
+        for name, kw in (("block_fp64", dict(precision=thm.THM_FP64)),
+                         ("block_fp32_refine", dict(precision=thm.THM_FP32_IR)),
+                         ("full_fp64", dict(precision=thm.THM_FP64, precond=thm.THM_PREC_FULL))):
+            o = thm.default_opts(rtol=1e-8, restart=50, **kw)
+            thm.thm_gmres_solve([S], o)  # setup (factorisation, correction, graph)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            (_,), (st,) = thm.thm_gmres_solve([S], o)
+            torch.cuda.synchronize()
+            row[name] = {"iters": st["iters"], "s": time.perf_counter() - t0, "rel_residual": st["rel_residual"],
+                         "refinements": st["refinements"]}
+        log(args, f"block w={w}: {row}")
+        rows.append(row)
+        del S
+    print(json.dumps({"workload": f"block benchmark, unit square {m}x{m} quads, Nedelec degree 1, centre square "
+                                  f"[0.25,0.75]^2 with refractive index 1.516 (eps = n^2), air elsewhere, plane wave "
+                                  f"on x=0, impedance elsewhere, single domain, GMRES(50) to 1e-8",
+                      "data": "synthetic", "sweep": rows,
+                      "paper_t1_block_column": {"5": 43, "10": 49, "20": 33, "40": 32, "80": 28}}))
+
+
 def main():
     args = parse()
     if args.summarize_pmc:
@@ -255,6 +287,9 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "c4":
         run_batch(args, thm, torch, workloads)
+        return
+    if args.workload == "block":
+        run_block_sweep(args, thm, torch, workloads)
         return
     if args.workload == "c3":
         m = args.mesh or 32
