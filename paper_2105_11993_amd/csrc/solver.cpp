@@ -539,7 +539,10 @@ void Ctx::build_full() {
             moff[s] = moff[rep[s]];
         }
     }
-    if (maxr > INT32_MAX / 4) fail(THM_EUNSUPPORTED, "boundary set too large for the complete inverse");
+    // M is inverted by the unblocked Gauss-Jordan of the setup (a rank-1 update of the whole
+    // 2r x 2r matrix per column, 16 (2r)^3 bytes of traffic): bounded to keep setup in seconds
+    if (maxr_rep > 1536)
+        fail(THM_EUNSUPPORTED, "boundary set too large for the complete inverse (more than 1536 DoFs carry C)");
     std::vector<float> cval32(cval.begin(), cval.end());
     full.goff.upload(goff, st);
     full.gam.upload(gam.empty() ? std::vector<int32_t>{0} : gam, st);
