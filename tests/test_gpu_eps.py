@@ -77,3 +77,27 @@ def test_block_benchmark_sweep_iterations_match_oracle(thm):
         print(f"  w={w}: gpu {st['iters']} oracle {it}", flush=True)
         assert st["status"] == 0
         assert abs(st["iters"] - it) <= 2
+
+
+def test_adjoint_gradient_with_eps(thm):
+    """dJ/dmu on the block benchmark (eps in the mass term, random mu): the adjoint kernel's
+    gradient equals the oracle's exact discrete gradient and central differences."""
+    from oracle import adjoint
+    d = workloads.block(m=16, omega=12.0)
+    d = dict(d, mu=np.random.default_rng(61).uniform(1.0, 2.0, 256))
+    print("case block adjoint 16", flush=True)
+    S = thm.thm_assemble(d)
+    opts = thm.default_opts(rtol=1e-13)
+    (E,), _ = thm.thm_gmres_solve([S], opts)
+    lo, hi = (0.6, 0.6, 0.0), (0.9, 0.9, 1.0)
+    g, J = thm.thm_adjoint_grad(S, E, lo, hi, opts)
+    so = system.assemble(problem(d))
+    Eo = system.solve_lu(so)
+    MT = adjoint.target_mass(so, lo, hi)
+    go, _ = adjoint.gradient(so, Eo, MT)
+    assert abs(J - adjoint.objective(so, Eo, MT)) <= 1e-10 * abs(J)
+    assert rel(g.cpu().numpy(), go) <= 1e-8
+    cells = workloads.fd_cells(so.mesh.n_cells, 6)
+    fd = adjoint.fd_gradient(problem(d), cells, lo, hi)
+    gc = g.cpu().numpy()[cells]
+    assert (np.abs(gc - fd) / np.maximum(np.abs(fd), 1e-3 * np.abs(fd).max())).max() <= 1e-6
