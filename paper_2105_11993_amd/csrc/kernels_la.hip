@@ -126,33 +126,35 @@ __global__ void __launch_bounds__(256) k_spmv_sell(const MatDesc *__restrict__ m
     const int64_t slice = (int64_t)(blockIdx.x - blkoff[s]) * 4 + (threadIdx.x >> 6);
     if (slice * SELL_C >= m.n) return;  // whole wave
     const int lane = threadIdx.x & 63;
-    const int32_t row = m.sl_row[slice * SELL_C + lane];
+    // the matrix (values, columns, row map) and y are touched once per call: non-temporal
+    // loads and stores keep them from evicting the gathered entries of x from the caches
+    const int32_t row = __builtin_nontemporal_load(m.sl_row + slice * SELL_C + lane);
     const T2 *x = reinterpret_cast<const T2 *>(xb + off[s]);
     const int32_t e0 = m.sl_ptr[slice], w = (m.sl_ptr[slice + 1] - e0) / SELL_C;
     const int32_t *cp = m.sl_col + e0 + lane;
     const T *vp = reinterpret_cast<const T *>(m.sl_val) + e0 + lane;
     T ar = 0, ai = 0;
     int k = 0;
-    for (; k + 4 <= w; k += 4) {
-        int32_t c[4];
-        T v[4];
+    for (; k + 8 <= w; k += 8) {
+        int32_t c[8];
+        T v[8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            c[u] = cp[(k + u) * SELL_C];
-            v[u] = vp[(k + u) * SELL_C];
+        for (int u = 0; u < 8; ++u) {
+            c[u] = __builtin_nontemporal_load(cp + (k + u) * SELL_C);
+            v[u] = __builtin_nontemporal_load(vp + (k + u) * SELL_C);
         }
-        T2 xv[4];
+        T2 xv[8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) xv[u] = x[c[u]];
+        for (int u = 0; u < 8; ++u) xv[u] = x[c[u]];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 8; ++u) {
             ar += v[u] * xv[u].x;
             ai += v[u] * xv[u].y;
         }
     }
     for (; k < w; ++k) {
-        const T v = vp[k * SELL_C];
-        const T2 xv = x[cp[k * SELL_C]];
+        const T v = __builtin_nontemporal_load(vp + k * SELL_C);
+        const T2 xv = x[__builtin_nontemporal_load(cp + k * SELL_C)];
         ar += v * xv.x;
         ai += v * xv.y;
     }
@@ -168,10 +170,11 @@ __global__ void __launch_bounds__(256) k_spmv_sell(const MatDesc *__restrict__ m
     T2 *y = reinterpret_cast<T2 *>(yb + off[s]);
     if (bb) {
         const T2 bv = reinterpret_cast<const T2 *>(bb + off[s])[row];
-        y[row] = T2{bv.x - ar, bv.y - ai};
-    } else {
-        y[row] = T2{ar, ai};
+        ar = bv.x - ar;
+        ai = bv.y - ai;
     }
+    __builtin_nontemporal_store(ar, &y[row].x);
+    __builtin_nontemporal_store(ai, &y[row].y);
 }
 
 __global__ void __launch_bounds__(256) k_sell_fill(int64_t ne, const int32_t *__restrict__ src,
