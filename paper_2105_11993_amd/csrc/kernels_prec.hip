@@ -544,12 +544,24 @@ __device__ __forceinline__ void bcr_fetch_b(BcrStep<T, NNT> &o, const int64_t (&
     }
 }
 
+// One piece of M, read non-temporally: each matrix element is used by one block once per
+// application, so it should not evict the member vectors (the X operands, which every
+// row tile of a task reads again) from the caches.
+template <class T>
+__device__ __forceinline__ void load_piece_stream(const T *p, T (&v)[8], int h) {
+    typedef T vec16 __attribute__((ext_vector_type(16 / sizeof(T))));
+    typedef const __attribute__((address_space(1))) vec16 gvec16;
+    const vec16 x = __builtin_nontemporal_load((const gvec16 *)p);
+#pragma unroll
+    for (int t = 0; t < bcr_per<T>(); ++t) v[h * bcr_per<T>() + t] = x[t];
+}
+
 // M operands of one step: the row tile is stored in lane order (see k_repack), so piece
 // h of every lane of the wave is one contiguous 64 x 16-byte run.
 template <class T>
 __device__ __forceinline__ void bcr_fetch_a(const T *A, T (&v)[8]) {
 #pragma unroll
-    for (int h = 0; h < 8 / bcr_per<T>(); ++h) load_piece(A + h * 64 * bcr_per<T>(), v, h);
+    for (int h = 0; h < 8 / bcr_per<T>(); ++h) load_piece_stream(A + h * 64 * bcr_per<T>(), v, h);
 }
 
 template <class T, int WPB, int NNT>
