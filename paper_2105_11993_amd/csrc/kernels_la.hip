@@ -340,7 +340,14 @@ __global__ void __launch_bounds__(256) k_cgs_update(const int64_t *__restrict__ 
         for (int u = 0; u < CG; ++u) {
             const T2 *vc = reinterpret_cast<const T2 *>(V + (int64_t)min(c0 + u, j) * ld + base);
 #pragma unroll
-            for (int t = 0; t < PPT; ++t) v[u][t] = vc[clampi(p0 + t * 256 + threadIdx.x, np)];
+            for (int t = 0; t < PPT; ++t) {
+                // last read of the basis in this Arnoldi step (the next step streams the
+                // preconditioner and the operator first): non-temporal
+                typedef T vec2 __attribute__((ext_vector_type(2)));
+                const vec2 q = __builtin_nontemporal_load(
+                    reinterpret_cast<const vec2 *>(vc + clampi(p0 + t * 256 + threadIdx.x, np)));
+                v[u][t] = T2{q.x, q.y};
+            }
         }
 #pragma unroll
         for (int u = 0; u < CG; ++u) {
