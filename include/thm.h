@@ -62,8 +62,8 @@ typedef enum { THM_KRYLOV_COMPLEX = 0, THM_KRYLOV_REAL = 1 } thm_krylov;
  * M = I + i C_G P K^{-1} P^T (r x r complex, r = |Gamma|; stored once per distinct system).
  * One application costs two applications of K^{-1} plus an r x r complex product.  Use it
  * with THM_FP64: in FP32 the correction cancels and refinement needs many inner steps.
- * Supported for r <= 1536 per subdomain (THM_EUNSUPPORTED above: the setup inverts the
- * 2r x 2r real form of M with an unblocked Gauss-Jordan). */
+ * Supported for r <= 4096 per subdomain (THM_EUNSUPPORTED above: the setup inverts the
+ * dense 2r x 2r real form of M). */
 typedef enum { THM_PREC_BLOCK = 0, THM_PREC_FULL = 1 } thm_precond;
 
 /* Problem statement (paper Sec. 2, eq. (1); partition eq. (5)).  Copied by thm_assemble. */

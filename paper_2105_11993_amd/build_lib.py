@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libthm.so")
 SOURCES = ["topo.cpp", "solver.cpp", "precond.cpp", "thm_abi.cpp", "kernels_la.hip", "kernels_fe.hip", "kernels_prec.hip",
-           "kernels_full.hip",
+           "kernels_full.hip", "kernels_inv.hip",
            "kernels_ddm.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -272,6 +272,9 @@ struct InvDesc {
     int ldo;
 };
 void launch_invert_batched(const std::vector<InvDesc> &d, int32_t *status, hipStream_t st, DBuf<InvDesc> &scratch);
+// Same result with panels of 64 columns and rank-64 product updates (kernels_inv.hip); the
+// input A is overwritten, W is scratch (n x n).
+void launch_invert_blocked(const std::vector<InvDesc> &d, int32_t *status, hipStream_t st);
 // At (n x m, leading dimension ldt) = alpha * A^T, A (m x n, leading dimension lda)
 void launch_transpose(const double *A, int m, int n, int lda, double *At, int ldt, double alpha, hipStream_t st);
 void launch_compare(const void *a, const void *b, int64_t n8, int32_t *mismatch, hipStream_t st);

@@ -251,7 +251,6 @@ void setup_precond(const std::vector<thm_system *> &all, hipStream_t st, bool sh
         for (int k = 0; k < L.nlayers; ++k) W[g].pos.push_back(k);
     }
     DBuf<GemmDesc> gscr;
-    DBuf<InvDesc> iscr;
     Sched gsched;
     auto run_gemms = [&](const std::vector<GemmDesc> &g) {
         launch_gemm_batched(g, st, gscr, gsched);
@@ -273,7 +272,7 @@ void setup_precond(const std::vector<thm_system *> &all, hipStream_t st, bool sh
             o += 2 * (int64_t)n * n;
             op += 2 * n;
         }
-        launch_invert_batched(d, status.p, st, iscr);
+        launch_invert_blocked(d, status.p, st);
     };
     const bool progress = std::getenv("THM_PROGRESS") != nullptr;
     if (progress)

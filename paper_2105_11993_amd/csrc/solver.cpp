@@ -541,8 +541,8 @@ void Ctx::build_full() {
     }
     // M is inverted by the unblocked Gauss-Jordan of the setup (a rank-1 update of the whole
     // 2r x 2r matrix per column, 16 (2r)^3 bytes of traffic): bounded to keep setup in seconds
-    if (maxr_rep > 1536)
-        fail(THM_EUNSUPPORTED, "boundary set too large for the complete inverse (more than 1536 DoFs carry C)");
+    if (maxr_rep > 4096)
+        fail(THM_EUNSUPPORTED, "boundary set too large for the complete inverse (more than 4096 DoFs carry C)");
     std::vector<float> cval32(cval.begin(), cval.end());
     full.goff.upload(goff, st);
     full.gam.upload(gam.empty() ? std::vector<int32_t>{0} : gam, st);
@@ -599,8 +599,7 @@ void Ctx::build_full() {
             jobs.push_back({2 * r, Bm.p + bo, Wk.p + bo, Inv.p + bo, piv.p + 4 * maxr_rep * (int64_t)q, 2 * r});
             bo += 4 * (int64_t)r * r;
         }
-        DBuf<InvDesc> iscr;
-        launch_invert_batched(jobs, status.p, st, iscr);
+        launch_invert_blocked(jobs, status.p, st);
         int32_t hs = 0;
         THM_HIP(hipMemcpyAsync(&hs, status.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         THM_HIP(hipStreamSynchronize(st));
