@@ -37,7 +37,7 @@ def parse():
     ap.add_argument("--scale", type=int, default=1, help="c4: divide every mesh size by this")
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--skip-full", action="store_true",
-                    help="skip the complete-inverse preconditioner ablation (c2)")
+                    help="skip the complete-inverse preconditioner ablation (c2, c3)")
     ap.add_argument("--restart", type=int, default=64)
     ap.add_argument("--max-outer", type=int, default=500, help="cap on outer iterations (profiling runs)")
     ap.add_argument("--inner-rtol", type=float, default=1e-10,
@@ -365,7 +365,7 @@ def main():
     # ablation: the complete inverse of the block system (Sec. 3.2's alternative) as the
     # subdomain preconditioner, applied exactly through K^{-1} and a boundary correction
     result_full = None
-    if not args.only_fast and not args.skip_full and args.workload == "c2":
+    if not args.only_fast and not args.skip_full:
         result_full = {"preconditioner": "complete inverse (K + iC)^{-1}: K^{-1} plus the boundary correction "
                                          "(THM_PREC_FULL); an ablation, not the benchmark form"}
         stf = None
