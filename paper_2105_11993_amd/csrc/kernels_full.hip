@@ -121,6 +121,7 @@ __global__ void __launch_bounds__(256) k_full_mv(int ns, const int32_t *__restri
     if (mask && !mask[s]) return;
     const int64_t g0 = goff[s];
     const int r = (int)(goff[s + 1] - g0);
+    if (r == 0) return;  // no boundary DoFs: nothing to correct (same for the whole block)
     const int ntile = (r + 255) / 256;
     const int tile = blockIdx.x % ntile, c = blockIdx.x / ntile;
     const int j0 = c * FULL_CW;
