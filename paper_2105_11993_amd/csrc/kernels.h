@@ -266,14 +266,13 @@ void launch_gemm_batched(const std::vector<GemmDesc> &g, hipStream_t st, DBuf<Ge
 
 struct InvDesc {
     int n;
-    double *A, *W;             // ping-pong buffers (n x n); input in A
+    double *A, *W;             // input A (n x n, overwritten); W is scratch (n x n)
     double *out;               // final inverse (n x n, leading dimension ldo)
     int32_t *piv;              // 2n: pivot rows, then the column permutation
     int ldo;
 };
-void launch_invert_batched(const std::vector<InvDesc> &d, int32_t *status, hipStream_t st, DBuf<InvDesc> &scratch);
-// Same result with panels of 64 columns and rank-64 product updates (kernels_inv.hip); the
-// input A is overwritten, W is scratch (n x n).
+// Batched Gauss-Jordan inversion with partial pivoting in panels of 64 columns and rank-64
+// product updates (kernels_inv.hip); status |= 1 for a zero or non-finite pivot.
 void launch_invert_blocked(const std::vector<InvDesc> &d, int32_t *status, hipStream_t st);
 // At (n x m, leading dimension ldt) = alpha * A^T, A (m x n, leading dimension lda)
 void launch_transpose(const double *A, int m, int n, int lda, double *At, int ldt, double alpha, hipStream_t st);

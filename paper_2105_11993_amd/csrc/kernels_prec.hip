@@ -237,122 +237,6 @@ void launch_gemm_batched(const std::vector<GemmDesc> &g, hipStream_t st, DBuf<Ge
     THM_HIP(hipGetLastError());
 }
 
-// ------------------------------------------------------------------ batched Gauss-Jordan inversion
-__global__ void k_gj_pivot(const InvDesc *ds, int nd, int col, int parity, int32_t *status) {
-    __shared__ double bv[256];
-    __shared__ int bi[256];
-    const int di = blockIdx.x;
-    if (di >= nd) return;
-    const InvDesc d = ds[di];
-    if (col >= d.n) return;
-    const double *A = parity ? d.W : d.A;
-    double best = -1.0;
-    int bidx = col;
-    for (int i = col + threadIdx.x; i < d.n; i += blockDim.x) {
-        const double v = fabs(A[(int64_t)i * d.n + col]);
-        if (v > best) { best = v; bidx = i; }
-    }
-    bv[threadIdx.x] = best;
-    bi[threadIdx.x] = bidx;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) {
-            const double v2 = bv[threadIdx.x + o];
-            const int i2 = bi[threadIdx.x + o];
-            if (v2 > bv[threadIdx.x] || (v2 == bv[threadIdx.x] && i2 < bi[threadIdx.x])) {
-                bv[threadIdx.x] = v2;
-                bi[threadIdx.x] = i2;
-            }
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        d.piv[col] = bi[0];
-        if (!(bv[0] > 0.0) || !isfinite(bv[0])) atomicOr(status, 1);
-    }
-}
-
-// One block per (row i, 256-column chunk) of each matrix: no per-element division.
-__global__ void __launch_bounds__(256) k_gj_update(const InvDesc *__restrict__ ds, const int32_t *__restrict__ blkoff,
-                                                   int nd, int col, int parity) {
-    const int di = find_sys2(blkoff, nd, blockIdx.x);
-    const InvDesc d = ds[di];
-    const int n = d.n;
-    if (col >= n) return;
-    const int nch = (n + 255) / 256;
-    const int local = blockIdx.x - blkoff[di];
-    const int i = local / nch;
-    const int j = (local - i * nch) * 256 + threadIdx.x;
-    if (i >= n || j >= n) return;
-    const double *Ain = parity ? d.W : d.A;
-    double *Aout = parity ? d.A : d.W;
-    const int p = d.piv[col];
-    const double pv = Ain[(int64_t)p * n + col];
-    const double ipv = pv != 0.0 ? 1.0 / pv : 0.0;
-    const double pr = (j == col) ? ipv : Ain[(int64_t)p * n + j] * ipv;
-    double out;
-    if (i == col) {
-        out = pr;
-    } else {
-        const int src = (i == p) ? col : i;
-        const double f = Ain[(int64_t)src * n + col];
-        const double e = (j == col) ? 0.0 : Ain[(int64_t)src * n + j];
-        out = e - f * pr;
-    }
-    Aout[(int64_t)i * n + j] = out;
-}
-
-__global__ void k_gj_perm_build(const InvDesc *ds, int nd) {
-    const int di = blockIdx.x * blockDim.x + threadIdx.x;
-    if (di >= nd) return;
-    const InvDesc d = ds[di];
-    int32_t *perm = d.piv + d.n;
-    for (int j = 0; j < d.n; ++j) perm[j] = j;
-    for (int c = d.n - 1; c >= 0; --c) {
-        const int p = d.piv[c];
-        const int32_t t = perm[c];
-        perm[c] = perm[p];
-        perm[p] = t;
-    }
-}
-
-__global__ void __launch_bounds__(256) k_gj_perm_apply(const InvDesc *__restrict__ ds,
-                                                       const int32_t *__restrict__ blkoff, int nd) {
-    const int di = find_sys2(blkoff, nd, blockIdx.x);
-    const InvDesc d = ds[di];
-    const int n = d.n;
-    const int nch = (n + 255) / 256;
-    const int local = blockIdx.x - blkoff[di];
-    const int i = local / nch;
-    const int j = (local - i * nch) * 256 + threadIdx.x;
-    if (i >= n || j >= n) return;
-    const double *res = (n % 2 == 0) ? d.A : d.W;
-    d.out[(int64_t)i * d.ldo + j] = res[(int64_t)i * n + d.piv[n + j]];
-}
-
-void launch_invert_batched(const std::vector<InvDesc> &d, int32_t *status, hipStream_t st, DBuf<InvDesc> &scratch) {
-    if (d.empty()) return;
-    int nmax = 0;
-    std::vector<int64_t> blocks(d.size());
-    for (size_t i = 0; i < d.size(); ++i) {
-        nmax = std::max(nmax, d[i].n);
-        blocks[i] = (int64_t)d[i].n * ((d[i].n + 255) / 256);
-    }
-    Sched sc;
-    sc.build(blocks, 1, st);
-    scratch.upload(d, st);
-    const int nd = (int)d.size();
-    for (int col = 0; col < nmax; ++col) {
-        const int parity = col & 1;
-        k_gj_pivot<<<nd, 256, 0, st>>>(scratch.p, nd, col, parity, status);
-        k_gj_update<<<sc.nblocks, 256, 0, st>>>(scratch.p, sc.blkoff.p, nd, col, parity);
-    }
-    k_gj_perm_build<<<(nd + 63) / 64, 64, 0, st>>>(scratch.p, nd);
-    k_gj_perm_apply<<<sc.nblocks, 256, 0, st>>>(scratch.p, sc.blkoff.p, nd);
-    THM_HIP(hipGetLastError());
-    THM_HIP(hipStreamSynchronize(st));  // keeps the schedule alive until the kernels finished
-}
-
 __global__ void k_transpose(const double *A, int m, int n, int lda, double *At, int ldt, double alpha) {
     __shared__ double t[32][33];
     const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
