@@ -502,6 +502,11 @@ __device__ __forceinline__ void bcr_tile(const BcrTask &tk, BcrShared<T, WPB> &s
         bcr_fetch_a(A0 + (int64_t)BCR_RT * kbeg, p.a0);
         bcr_fetch_a(A1 + (int64_t)BCR_RT * kbeg, p.a1);
     }
+    // Any active member in this chunk: one flag per lane, the same ballot in every wave,
+    // so the whole block leaves together.  It is taken after the first M request, which
+    // depends on the task alone, so that the member and mask lookups overlap it.
+    const bool on = lane < 8 * NNT && mb + lane < m1 && (!mask || mask[memb[mb + lane]]);
+    if (!__ballot(on)) return;
     constexpr int NOUT = BCR_RT * 16 * NNT;
     constexpr int NPT = (NOUT + 64 * WPB - 1) / (64 * WPB);  // outputs per thread
     if (tk.subtract) {
@@ -517,21 +522,24 @@ __device__ __forceinline__ void bcr_tile(const BcrTask &tk, BcrShared<T, WPB> &s
     for (int kc = threadIdx.x; kc < (tk.ld >> 3); kc += blockDim.x) bcr_tab[kc] = tk.tab[kc];
     __syncthreads();
     if (nst > 0) {
-        // two operand buffers in turn; the prefetch past the last step repeats the last
-        // step's addresses
+        // Two operand buffers in turn, two steps per trip with no exit between them: each
+        // buffer's loads are then issued a whole MFMA block before their use on every
+        // path (with an exit between the halves the compiler sinks the second buffer's
+        // loads below the first block).  The prefetch after the last step repeats the
+        // last step's addresses; the scheduling barriers keep each prefetch ahead of the
+        // MFMAs it overlaps.
         const int klast = kbeg + (nst - 1) * BCR_KS;
         bcr_fetch_b(p, bbase, kbeg, wsb, ysb);
-        // (the scheduling barriers keep the prefetch ahead of the MFMAs it overlaps)
-        for (int st = 0;; st += 2) {
-            bcr_fetch<T, WPB, NNT>(q, sh, bbase, A0, A1, min(kbeg + (st + 1) * BCR_KS, klast), wsb, ysb);
+        int st = 0;
+        for (; st + 2 <= nst; st += 2) {
+            bcr_fetch<T, WPB, NNT>(q, sh, bbase, A0, A1, kbeg + (st + 1) * BCR_KS, wsb, ysb);
             __builtin_amdgcn_sched_barrier(0);
             bcr_mma(p, acc);
-            if (st + 1 >= nst) break;
             bcr_fetch<T, WPB, NNT>(p, sh, bbase, A0, A1, min(kbeg + (st + 2) * BCR_KS, klast), wsb, ysb);
             __builtin_amdgcn_sched_barrier(0);
             bcr_mma(q, acc);
-            if (st + 2 >= nst) break;
         }
+        if (st < nst) bcr_mma(p, acc);
     }
     // Sum of the waves' partial tiles in a fixed order: the upper half of the waves
     // store, the lower half adds and stores, then every thread sums the WPB/2 slots.
@@ -599,10 +607,6 @@ __global__ void __launch_bounds__(64 * WPB, BcrOcc<T>::v) k_bcr_mfma(const BcrTa
     const int rt = local / tk.nmc, mchunk = local - rt * tk.nmc;
     const int m1 = tk.mend;
     const int mb = tk.mbeg + mchunk * 8 * tk.nnt;
-    // any active member in this chunk: one flag per lane, the same ballot in every wave
-    const int lane = threadIdx.x & 63;
-    const bool on = lane < 8 * tk.nnt && mb + lane < m1 && (!mask || mask[memb[mb + lane]]);
-    if (!__ballot(on)) return;  // same decision in every thread of the block
     if (tk.nnt == 1)
         bcr_tile<T, WPB, 1>(tk, sh, rt * BCR_RT, mb, m1, memb, msoff, mask, wsb, ysb);
     else
