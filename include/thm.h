@@ -142,7 +142,13 @@ typedef struct {
     int64_t n_interface;     /* complex interface unknowns of the DDM (sum over directed interfaces; -1 before
                                 the first DDM solve) */
     int32_t spmv_variant;    /* autotuned FP64 SpMV variant of this system's context (10 x lanes per row +
-                                unroll for CSR-vector, 19 for SELL-64), -1 before the first solve */
+                                unroll for CSR-vector, 19 for SELL-64, 20 for grouped SELL-64), -1 before
+                                the first solve */
+    int32_t ddm_spmv_variant; /* FP64 SpMV variant of the DDM's batched subdomain context, -1 before the
+                                 first DDM solve */
+    int32_t ddm_spmv_groups;  /* groups of subdomains with the same K in that context (each group shares
+                                 one read of K in the grouped SELL-64 product), -1 before the first DDM
+                                 solve */
 } thm_info;
 
 typedef struct thm_system thm_system;
@@ -240,11 +246,19 @@ thm_status thm_time_spmv(thm_system *sys, int32_t precision, int32_t reps, doubl
  * (code 10 L + U, L in {2, 4, 8, 16, 32, 64}, U in {1, 4}; L = 64 only with U = 1) or
  * SELL-64 (code 19: one wave per slice of 64 rows, column-major padded entries). */
 #define THM_SPMV_SELL 19
+/* Grouped SELL-64 (code 20): systems of a batch whose K (pattern, values and Dirichlet
+ * set) are identical -- the subdomains of a uniform decomposition, say -- form groups of
+ * at most 16, and one wave applies a slice of the shared K to every member's vector, so
+ * K is read once per group instead of once per system; each member's C is applied from
+ * its own rows.  Results are bitwise those of code 19. */
+#define THM_SPMV_SELL_GROUP 20
 
 /* Pin the SpMV variant of the single-system context of `sys` (the one used by
- * thm_gmres_solve on {sys}, thm_apply_operator and thm_time_spmv), overriding the
- * autotuner's choice for that precision; variant = -1 re-runs the autotuner.  Returns
- * THM_EINVAL for an unknown variant or precision. */
+ * thm_gmres_solve on {sys}, thm_apply_operator and thm_time_spmv) and, once a DDM solve
+ * has built it, of the DDM's batched subdomain context, overriding the autotuner's
+ * choice for that precision; variant = -1 re-runs the autotuner.  Captured GMRES step
+ * graphs of those contexts are dropped, so the next solve uses the new variant.
+ * Returns THM_EINVAL for an unknown variant or precision. */
 thm_status thm_set_spmv_variant(thm_system *sys, int32_t precision, int32_t variant);
 
 /* Average device time (ms) of `reps` applications of the block cyclic-reduction

@@ -58,7 +58,8 @@ class ThmInfo(ctypes.Structure):
     _fields_ = [("n_dofs", ctypes.c_int64), ("n_free", ctypes.c_int64), ("nnz", ctypes.c_int64),
                 ("nnz_c", ctypes.c_int64), ("n_cells", ctypes.c_int64), ("n_subdomains", ctypes.c_int32),
                 ("n_layers", ctypes.c_int32), ("factor_bytes", ctypes.c_int64), ("n_interface", ctypes.c_int64),
-                ("spmv_variant", ctypes.c_int32)]
+                ("spmv_variant", ctypes.c_int32), ("ddm_spmv_variant", ctypes.c_int32),
+                ("ddm_spmv_groups", ctypes.c_int32)]
 
 
 EXPORTS = ["thm_default_opts", "thm_assemble", "thm_gmres_solve", "thm_ddm_solve", "thm_adjoint_grad",
@@ -66,7 +67,8 @@ EXPORTS = ["thm_default_opts", "thm_assemble", "thm_gmres_solve", "thm_ddm_solve
            "thm_apply_precond", "thm_export_matrices", "thm_export_rhs", "thm_export_elements", "thm_time_spmv",
            "thm_time_precond", "thm_set_spmv_variant", "thm_apply_precond_full"]
 THM_SPMV_SELL = 19
-SPMV_VARIANTS = [21, 41, 81, 161, 321, 641, 24, 44, 84, 164, 324, THM_SPMV_SELL]
+THM_SPMV_SELL_GROUP = 20
+SPMV_VARIANTS = [21, 41, 81, 161, 321, 641, 24, 44, 84, 164, 324, THM_SPMV_SELL, THM_SPMV_SELL_GROUP]
 
 
 def load_library(path=LIB_PATH):

@@ -25,6 +25,17 @@ struct MatDesc {
 constexpr int SELL_C = 64;        // rows per slice (one wave, one row per lane)
 constexpr int SELL_SIGMA = 1024;  // sorting window (rows)
 constexpr int SPMV_SELL = 19;     // SpMV variant code of the SELL-64 kernel (256 rows per block)
+// Grouped SELL-64 (variant code SPMV_SELL_GROUP): systems of a batch with the same K share
+// one read of it per product.  A group holds at most SPMV_GMAX systems.
+constexpr int SPMV_SELL_GROUP = 20;
+constexpr int SPMV_GMAX = 16;
+struct SpmvGroup {
+    int32_t rep;                 // system whose SELL arrays hold the shared K
+    int32_t nm;                  // member systems (1 .. SPMV_GMAX)
+    int32_t npad;                // nm rounded up to 4, 8, 12 or 16 (npad / 4 waves per slice)
+    int32_t mem[SPMV_GMAX];      // member system indices
+    const uint8_t *crow;         // per row of K: 1 if some member's C row has entries
+};
 // Host: SELL-64 layout of a CSR pattern; src[e] = CSR index of entry e, or -1 (padding).
 void sell_build(int64_t n, const std::vector<int32_t> &rowptr, const std::vector<int32_t> &col,
                 std::vector<int32_t> &ptr, std::vector<int32_t> &scol, std::vector<int32_t> &src,
@@ -95,6 +106,12 @@ struct Batch {
 template <class T>
 void launch_spmv(int lpr, const MatDesc *mats, const int64_t *off, const Sched &sc, int ns, const int32_t *mask,
                  const T *x, T *y, const T *b, float csign, hipStream_t st);
+// Grouped SELL-64 product over the groups of a batch (schedule: one unit per wave, i.e.
+// slices of the representative times npad / 4, four units per block); same arguments as
+// launch_spmv otherwise.
+template <class T>
+void launch_spmv_group(const MatDesc *mats, const int64_t *off, const SpmvGroup *groups, const Sched &sc, int ng,
+                       const int32_t *mask, const T *x, T *y, const T *b, float csign, hipStream_t st);
 template <class T>
 void launch_dots(const Batch &B, const int32_t *mask, const int32_t *jcnt, const T *V, int64_t ld, const T *w,
                  double *part, int cplx, hipStream_t st);

@@ -220,6 +220,136 @@ template void launch_spmv<double>(int, const MatDesc *, const int64_t *, const S
 template void launch_spmv<float>(int, const MatDesc *, const int64_t *, const Sched &, int, const int32_t *,
                                  const float *, float *, const float *, float, hipStream_t);
 
+// Grouped SELL-64 variant: the systems of a group have the same K (pattern and values).
+// A slice of 64 rows is served by up to four waves of one block, each applying it to four
+// members' vectors (the group's count padded to a multiple of 4; the padding repeats the
+// last member and is not stored), so K goes from HBM once per slice and its re-reads by
+// the sibling waves hit the caches.  The sum over a row runs in the same order as in
+// k_spmv_sell, so both variants give the same bits.  Each member's boundary operator C is
+// applied from its own CSR, on the rows where some member has C entries.
+template <class T, int U>
+__device__ __forceinline__ void spmv_group_slice(const MatDesc *__restrict__ mats, const int64_t *__restrict__ off,
+                                                 const SpmvGroup &G, int j0, const MatDesc &m, int64_t slice,
+                                                 const int32_t *__restrict__ mask, const T *__restrict__ xb,
+                                                 T *__restrict__ yb, const T *__restrict__ bb, float csign) {
+    using T2 = typename V2<T>::t;
+    constexpr int MB = 4;
+    const int nmw = min(MB, G.nm - j0);  // members of this wave (1 .. 4)
+    const int lane = threadIdx.x & 63;
+    const int32_t row = __builtin_nontemporal_load(m.sl_row + slice * SELL_C + lane);
+    const int32_t e0 = m.sl_ptr[slice], w = (m.sl_ptr[slice + 1] - e0) / SELL_C;
+    const int32_t *cp = m.sl_col + e0 + lane;
+    const T *vp = reinterpret_cast<const T *>(m.sl_val) + e0 + lane;
+    const T2 *x[MB];
+#pragma unroll
+    for (int j = 0; j < MB; ++j) x[j] = reinterpret_cast<const T2 *>(xb + off[G.mem[j0 + min(j, nmw - 1)]]);
+    T ar[MB], ai[MB];
+#pragma unroll
+    for (int j = 0; j < MB; ++j) ar[j] = ai[j] = 0;
+    int k = 0;
+    for (; k + U <= w; k += U) {
+        int32_t c[U];
+        T v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            c[u] = cp[(k + u) * SELL_C];
+            v[u] = vp[(k + u) * SELL_C];
+        }
+        T2 xv[MB][U];
+#pragma unroll
+        for (int j = 0; j < MB; ++j)
+#pragma unroll
+            for (int u = 0; u < U; ++u) xv[j][u] = x[j][c[u]];
+#pragma unroll
+        for (int j = 0; j < MB; ++j)
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                ar[j] += v[u] * xv[j][u].x;
+                ai[j] += v[u] * xv[j][u].y;
+            }
+    }
+    for (; k < w; ++k) {
+        const T v = vp[k * SELL_C];
+        const int32_t c = cp[k * SELL_C];
+#pragma unroll
+        for (int j = 0; j < MB; ++j) {
+            const T2 xv = x[j][c];
+            ar[j] += v * xv.x;
+            ai[j] += v * xv.y;
+        }
+    }
+    if (row < 0) return;
+    if (G.crow[row]) {
+        const T sg = (T)csign;
+#pragma unroll
+        for (int j = 0; j < MB; ++j) {
+            if (j >= nmw) break;
+            const MatDesc &mj = mats[G.mem[j0 + j]];
+            const T *cv = reinterpret_cast<const T *>(mj.cval);
+            for (int32_t q = mj.crowptr[row]; q < mj.crowptr[row + 1]; ++q) {
+                const T c = sg * cv[q];
+                const T2 xv = x[j][mj.ccol[q]];
+                ar[j] -= c * xv.y;
+                ai[j] += c * xv.x;
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < MB; ++j) {
+        if (j >= nmw) break;
+        const int s = G.mem[j0 + j];
+        if (mask && !mask[s]) continue;
+        T a = ar[j], b = ai[j];
+        if (bb) {
+            const T2 bv = reinterpret_cast<const T2 *>(bb + off[s])[row];
+            a = bv.x - a;
+            b = bv.y - b;
+        }
+        T2 *y = reinterpret_cast<T2 *>(yb + off[s]);
+        __builtin_nontemporal_store(a, &y[row].x);
+        __builtin_nontemporal_store(b, &y[row].y);
+    }
+}
+
+// Block schedule: npad / 4 consecutive waves per slice (see SpmvGroup).
+template <class T>
+__global__ void __launch_bounds__(256) k_spmv_sell_group(const MatDesc *__restrict__ mats,
+                                                         const int64_t *__restrict__ off,
+                                                         const SpmvGroup *__restrict__ groups,
+                                                         const int32_t *__restrict__ blkoff, int ng,
+                                                         const int32_t *__restrict__ mask,
+                                                         const T *__restrict__ xb, T *__restrict__ yb,
+                                                         const T *__restrict__ bb, float csign) {
+    const int g = find_sys(blkoff, ng, blockIdx.x);
+    const SpmvGroup &G = groups[g];
+    const int nmc = G.npad / 4;
+    const int64_t gw = (int64_t)(blockIdx.x - blkoff[g]) * 4 + (threadIdx.x >> 6);
+    const int64_t slice = gw / nmc;
+    const int j0 = 4 * (int)(gw - slice * nmc);
+    const MatDesc &m = mats[G.rep];
+    if (slice * SELL_C >= m.n) return;  // whole wave
+    if (mask) {
+        int any = 0;
+        for (int j = j0; j < min(j0 + 4, G.nm); ++j) any |= mask[G.mem[j]];
+        if (!any) return;
+    }
+    constexpr int U = sizeof(T) == 4 ? 4 : 2;
+    spmv_group_slice<T, U>(mats, off, G, j0, m, slice, mask, xb, yb, bb, csign);
+}
+
+template <class T>
+void launch_spmv_group(const MatDesc *mats, const int64_t *off, const SpmvGroup *groups, const Sched &sc, int ng,
+                       const int32_t *mask, const T *x, T *y, const T *b, float csign, hipStream_t st) {
+    if (!sc.nblocks) return;
+    k_spmv_sell_group<T><<<sc.nblocks, 256, 0, st>>>(mats, off, groups, sc.blkoff.p, ng, mask, x, y, b, csign);
+    THM_HIP(hipGetLastError());
+}
+template void launch_spmv_group<double>(const MatDesc *, const int64_t *, const SpmvGroup *, const Sched &, int,
+                                        const int32_t *, const double *, double *, const double *, float,
+                                        hipStream_t);
+template void launch_spmv_group<float>(const MatDesc *, const int64_t *, const SpmvGroup *, const Sched &, int,
+                                       const int32_t *, const float *, float *, const float *, float, hipStream_t);
+
 // ------------------------------------------------------------------ Krylov vector kernels
 // Vectors are interleaved (re, im) pairs.  With cplx = 1 the Arnoldi process uses
 // complex scalars (h = <v, w> = sum conj(v) w; the Krylov space is invariant under

@@ -42,6 +42,10 @@ static bool same_values(thm_system &a, thm_system &b, hipStream_t st) {
     return h == 0;
 }
 
+bool same_matrices(thm_system &a, thm_system &b, hipStream_t st) {
+    return same_topology(a, b) && a.K.rowptr == b.K.rowptr && a.K.col == b.K.col && same_values(a, b, st);
+}
+
 namespace {
 // Work of one factor during setup.
 struct Work {

@@ -263,8 +263,67 @@ void Ctx::build(const std::vector<thm_system *> &s, int m, hipStream_t stream) {
     bnorm64.alloc(ns);
     resid64.alloc(ns);
     THM_HIP(hipStreamSynchronize(st));
+    build_groups();
     autotune();
 }
+
+// Groups of systems with the same K, in batch order, at most SPMV_GMAX each.
+void Ctx::build_groups() {
+    std::vector<std::vector<int>> mem;
+    std::vector<int> rep;
+    for (int i = 0; i < ns; ++i) {
+        int g = -1;
+        for (size_t q = 0; q < rep.size() && g < 0; ++q)
+            if ((int)mem[q].size() < SPMV_GMAX && same_matrices(*sys[rep[q]], *sys[i], st)) g = (int)q;
+        if (g < 0) {
+            rep.push_back(i);
+            mem.emplace_back();
+            g = (int)rep.size() - 1;
+        }
+        mem[g].push_back(i);
+    }
+    ngroups = (int)rep.size();
+    spmv_shared = false;
+    std::vector<int64_t> coff(ngroups + 1, 0), rows(ngroups), waves(ngroups);
+    for (int g = 0; g < ngroups; ++g) {
+        rows[g] = sys[rep[g]]->n;
+        waves[g] = (rows[g] + SELL_C - 1) / SELL_C * (int64_t)(((int)mem[g].size() + 3) / 4);
+        coff[g + 1] = coff[g] + ((rows[g] + 255) & ~int64_t(255));
+        spmv_shared |= mem[g].size() > 1;
+    }
+    std::vector<uint8_t> crow(coff[ngroups], 0);
+    for (int g = 0; g < ngroups; ++g)
+        for (int i : mem[g]) {
+            const std::vector<int32_t> &rp = sys[i]->C.rowptr;
+            for (int64_t r = 0; r < rows[g]; ++r)
+                if (rp[r + 1] > rp[r]) crow[coff[g] + r] = 1;
+        }
+    sgcrow.upload(crow, st);
+    std::vector<SpmvGroup> h(ngroups);
+    for (int g = 0; g < ngroups; ++g) {
+        SpmvGroup &G = h[g];
+        G.rep = rep[g];
+        G.nm = (int32_t)mem[g].size();
+        G.npad = (G.nm + 3) & ~3;
+        for (int j = 0; j < SPMV_GMAX; ++j) G.mem[j] = mem[g][std::min(j, G.nm - 1)];
+        G.crow = sgcrow.p + coff[g];
+    }
+    sgroups.upload(h, st);
+    gsched.build(waves, 4, st);
+    THM_HIP(hipStreamSynchronize(st));
+}
+
+template <class T>
+void Ctx::spmv(int v, const int32_t *mask, const T *x, T *y, const T *b, float csign) {
+    const MatDesc *m = sizeof(T) == 8 ? mat64.p : mat32.p;
+    if (v == SPMV_SELL_GROUP) {
+        launch_spmv_group<T>(m, K.B.off.p, sgroups.p, gsched, ngroups, mask, x, y, b, csign, st);
+        return;
+    }
+    launch_spmv<T>(v, m, K.B.off.p, K.B.spmv_sched(v, st), ns, mask, x, y, b, csign, st);
+}
+template void Ctx::spmv<double>(int, const int32_t *, const double *, double *, const double *, float);
+template void Ctx::spmv<float>(int, const int32_t *, const float *, float *, const float *, float);
 
 // Preconditioner of the batch: factorisation (shared between identical systems) and the
 // batched apply schedule.  Built on first use, so SpMV-only uses of a context skip it.
@@ -635,8 +694,7 @@ KOps<double> Ctx::ops64(float csign, bool with_prec, int pkind) {
     if (with_prec && pkind == 1) build_full();
     KOps<double> o;
     o.apply = [this, csign](const double *x, double *y, const double *b, const int32_t *mask) {
-        const Sched &sc = K.B.spmv_sched(lpr64, st);
-        launch_spmv<double>(lpr64, mat64.p, K.B.off.p, sc, ns, mask, x, y, b, csign, st);
+        spmv<double>(lpr64, mask, x, y, b, csign);
     };
     o.prec = [this, csign, pkind](const double *x, double *y, const int32_t *mask) {
         if (!prec_ready) fail(THM_EINVAL, "preconditioner used before it was built");
@@ -676,8 +734,7 @@ KOps<float> Ctx::ops32(float csign, bool with_prec, int pkind) {
     }
     KOps<float> o;
     o.apply = [this, csign](const float *x, float *y, const float *b, const int32_t *mask) {
-        const Sched &sc = K.B.spmv_sched(lpr32, st);
-        launch_spmv<float>(lpr32, mat32.p, K.B.off.p, sc, ns, mask, x, y, b, csign, st);
+        spmv<float>(lpr32, mask, x, y, b, csign);
     };
     if (with_prec && pkind == 1) build_full();
     o.prec = [this, csign, pkind](const float *x, float *y, const int32_t *mask) {
@@ -885,8 +942,10 @@ static void tune_store() {
 }
 
 void Ctx::autotune() {
-    const int cand[] = {21, 41, 81, 161, 321, 24, 44, 84, 164, 324, SPMV_SELL};
-    for (int c : cand) K.B.spmv_sched(c, st);
+    std::vector<int> cand = {21, 41, 81, 161, 321, 24, 44, 84, 164, 324, SPMV_SELL};
+    if (spmv_shared) cand.push_back(SPMV_SELL_GROUP);
+    for (int c : cand)
+        if (c != SPMV_SELL_GROUP) K.B.spmv_sched(c, st);
     int64_t nnz = 0, nrows = 0;
     for (thm_system *s : sys) {
         nnz += (int64_t)s->K.col.size();
@@ -896,8 +955,8 @@ void Ctx::autotune() {
     int nb = 0;
     while ((int64_t(1) << (nb + 1)) <= nrows) ++nb;
     char key64[128], key32[128];
-    std::snprintf(key64, sizeof key64, "gfx950:d%d:p%d:n%d:b%d:fp64", s0.topo.dim, s0.topo.p, nb, ns);
-    std::snprintf(key32, sizeof key32, "gfx950:d%d:p%d:n%d:b%d:fp32", s0.topo.dim, s0.topo.p, nb, ns);
+    std::snprintf(key64, sizeof key64, "gfx950:d%d:p%d:n%d:b%d:g%d:fp64", s0.topo.dim, s0.topo.p, nb, ns, ngroups);
+    std::snprintf(key32, sizeof key32, "gfx950:d%d:p%d:n%d:b%d:g%d:fp32", s0.topo.dim, s0.topo.p, nb, ns, ngroups);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         tune_load();
@@ -924,19 +983,13 @@ void Ctx::autotune() {
     };
     float best = 1e30f;
     for (int c : cand) {
-        const Sched &sc = K.B.spmv_sched(c, st);
-        const float ms = time_it([&] {
-            launch_spmv<double>(c, mat64.p, K.B.off.p, sc, ns, nullptr, x64.p, r64.p, nullptr, 1.f, st);
-        });
+        const float ms = time_it([&] { spmv<double>(c, nullptr, x64.p, r64.p, nullptr, 1.f); });
         if (ms < best) { best = ms; lpr64 = c; }
     }
     ops32(1.f, false);
     best = 1e30f;
     for (int c : cand) {
-        const Sched &sc = K.B.spmv_sched(c, st);
-        const float ms = time_it([&] {
-            launch_spmv<float>(c, mat32.p, K.B.off.p, sc, ns, nullptr, x32.p, b32.p, nullptr, 1.f, st);
-        });
+        const float ms = time_it([&] { spmv<float>(c, nullptr, x32.p, b32.p, nullptr, 1.f); });
         if (ms < best) { best = ms; lpr32 = c; }
     }
     THM_HIP(hipEventDestroy(e0));

@@ -164,7 +164,16 @@ struct Ctx {
     int64_t fp64_fallbacks = 0;  // systems finished in FP64 after a failed refinement step (cumulative)
     std::vector<int32_t> last_fb;  // per system, last solve: finished in FP64
     DBuf<double> rnorm, bnorm64, resid64;
-    int lpr64 = 81, lpr32 = 81;  // SpMV variants (10 * lanes_per_row + unroll)
+    int lpr64 = 81, lpr32 = 81;  // SpMV variants (10 * lanes_per_row + unroll, or a SELL code)
+    // groups of systems with the same K for the grouped SELL product (SPMV_SELL_GROUP)
+    DBuf<SpmvGroup> sgroups;
+    DBuf<uint8_t> sgcrow;
+    Sched gsched;
+    int ngroups = 0;
+    bool spmv_shared = false;  // some group has two or more members
+    void build_groups();
+    // y = A x or y = b - A x with SpMV variant v (a code of launch_spmv or SPMV_SELL_GROUP)
+    template <class T> void spmv(int v, const int32_t *mask, const T *x, T *y, const T *b, float csign);
 
     bool prec_ready = false;
 
@@ -204,6 +213,9 @@ struct Ctx {
 };
 
 void setup_precond(const std::vector<thm_system *> &systems, hipStream_t st, bool share = true);
+// Same mesh, degree, Dirichlet set, K pattern and (bitwise) K values and element matrices:
+// the systems share a preconditioner factor and one read of K in the grouped SpMV.
+bool same_matrices(thm_system &a, thm_system &b, hipStream_t st);
 double now_ms();
 
 }  // namespace thm

@@ -1043,6 +1043,12 @@ thm_status thm_system_info(const thm_system *sys, thm_info *info) {
         info->factor_bytes = sys->fac ? sys->fac->bytes : -1;
         info->n_interface = sys->ddm ? sys->ddm->nent : -1;
         info->spmv_variant = -1;
+        info->ddm_spmv_variant = -1;
+        info->ddm_spmv_groups = -1;
+        if (sys->ddm && sys->ddm->inner) {
+            info->ddm_spmv_variant = sys->ddm->inner->lpr64;
+            info->ddm_spmv_groups = sys->ddm->inner->ngroups;
+        }
         {
             std::lock_guard<std::mutex> lk(g_cache_mu);
             auto it = g_ctx_cache.find(std::vector<thm_system *>{const_cast<thm_system *>(sys)});
@@ -1222,22 +1228,30 @@ thm_status thm_time_spmv(thm_system *sys, int32_t precision, int32_t reps, doubl
     });
 }
 
+static_assert(THM_SPMV_SELL == thm::SPMV_SELL && THM_SPMV_SELL_GROUP == thm::SPMV_SELL_GROUP,
+              "SpMV variant codes of the header and the kernels differ");
+
 thm_status thm_set_spmv_variant(thm_system *sys, int32_t precision, int32_t variant) {
     return guard([&] {
         if (!sys) fail(THM_EINVAL, "bad arguments");
         if (precision != THM_FP64 && precision != THM_FP32_IR) fail(THM_EINVAL, "unknown precision");
-        static const int known[] = {21, 41, 81, 161, 321, 641, 24, 44, 84, 164, 324, THM_SPMV_SELL};
+        static const int known[] = {21, 41, 81, 161, 321, 641, 24, 44, 84, 164, 324, THM_SPMV_SELL,
+                                    THM_SPMV_SELL_GROUP};
         bool ok = variant == -1;
         for (int k : known) ok = ok || k == variant;
         if (!ok) fail(THM_EINVAL, "unknown SpMV variant");
-        Ctx &c = get_ctx({sys}, 50);
-        if (variant == -1) {
-            c.autotune();
-            return;
-        }
-        c.K.B.spmv_sched(variant, c.st);
-        if (precision == THM_FP64) c.lpr64 = variant;
-        else c.lpr32 = variant;
+        auto pin = [&](Ctx &c) {
+            c.K.drop_graphs();  // captured steps hold the previous variant's kernel
+            if (variant == -1) {
+                c.autotune();
+                return;
+            }
+            if (variant != THM_SPMV_SELL_GROUP) c.K.B.spmv_sched(variant, c.st);
+            if (precision == THM_FP64) c.lpr64 = variant;
+            else c.lpr32 = variant;
+        };
+        pin(get_ctx({sys}, 50));
+        if (sys->ddm && sys->ddm->inner) pin(*sys->ddm->inner);
     });
 }
 
