@@ -393,6 +393,18 @@ def main():
         spmv[name] = {"ms": ms, "bytes": by, "GBps": by / ms / 1e6}
     spmv["variant_fp64"] = S.fresh_info()["spmv_variant"]
     log(args, f"spmv: {spmv}")
+    # the subdomain operators in one product, as the solve applies them: per-system SELL-64
+    # against the grouped form (subdomains with the same K read it once per group); the
+    # algorithmic bytes count each distinct K once for both
+    inf = S.fresh_info()
+    spmv_batch = None
+    if inf["ddm_spmv_groups"] >= 0:
+        spmv_batch = {"variant_fp64": inf["ddm_spmv_variant"], "groups": inf["ddm_spmv_groups"]}
+        for name, prec in (("fp64", thm.THM_FP64), ("fp32", thm.THM_FP32_IR)):
+            for vname, v in (("sell", thm.THM_SPMV_SELL), ("grouped", thm.THM_SPMV_SELL_GROUP)):
+                ms, by = thm.thm_time_spmv_batch(S, prec, v, reps=50)
+                spmv_batch[f"{name}_{vname}"] = {"ms": ms, "bytes": by, "GBps": by / ms / 1e6}
+        log(args, f"spmv batch: {spmv_batch}")
     # dominant kernel of the timed solve: the cyclic-reduction multi-GEMV of the batched
     # FP32 subdomain preconditioner (HIP events on the library stream, same launches as
     # inside the solve)
@@ -428,6 +440,7 @@ def main():
         "speedup_vs_plain_fp64": (result_plain["s"] / t_fast) if result_plain else None,
         "full_inverse_ablation": result_full,
         "spmv": spmv,
+        "spmv_batch": spmv_batch,
         "roofline": roof,
         "device_copy": copy,
     }

@@ -242,6 +242,15 @@ thm_status thm_export_elements(thm_system *sys, int64_t c0, int64_t count, doubl
 thm_status thm_time_spmv(thm_system *sys, int32_t precision, int32_t reps, double *ms_out,
                          double *bytes_out, void *stream);
 
+/* Average device time (ms) of `reps` block SpMVs of eq. (4) over every subdomain of the
+ * DDM's batched subdomain context (built by the first thm_ddm_solve on `sys`; THM_EINVAL
+ * before), all systems active, with SpMV variant `variant` (a code below, or -1 for the
+ * context's own choice), measured with HIP events on `stream`.  bytes_out: algorithmic
+ * bytes per product, the same for every variant: each distinct K (values, columns, row
+ * pointers) once, and per subdomain its C, its row pointers, x read once and y written
+ * once. */
+thm_status thm_time_spmv_batch(thm_system *sys, int32_t precision, int32_t variant, int32_t reps, double *ms_out,
+                               double *bytes_out, void *stream);
 /* Block SpMV variants of eq. (4)'s operator: CSR-vector with L lanes per row and unroll U
  * (code 10 L + U, L in {2, 4, 8, 16, 32, 64}, U in {1, 4}; L = 64 only with U = 1) or
  * SELL-64 (code 19: one wave per slice of 64 rows, column-major padded entries). */

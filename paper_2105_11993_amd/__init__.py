@@ -65,7 +65,7 @@ class ThmInfo(ctypes.Structure):
 EXPORTS = ["thm_default_opts", "thm_assemble", "thm_gmres_solve", "thm_ddm_solve", "thm_adjoint_grad",
            "thm_system_info", "thm_system_set_mu", "thm_system_destroy", "thm_last_error", "thm_apply_operator",
            "thm_apply_precond", "thm_export_matrices", "thm_export_rhs", "thm_export_elements", "thm_time_spmv",
-           "thm_time_precond", "thm_set_spmv_variant", "thm_apply_precond_full"]
+           "thm_time_precond", "thm_set_spmv_variant", "thm_apply_precond_full", "thm_time_spmv_batch"]
 THM_SPMV_SELL = 19
 THM_SPMV_SELL_GROUP = 20
 SPMV_VARIANTS = [21, 41, 81, 161, 321, 641, 24, 44, 84, 164, 324, THM_SPMV_SELL, THM_SPMV_SELL_GROUP]
@@ -93,6 +93,7 @@ def load_library(path=LIB_PATH):
         "thm_export_rhs": (i32, [vp, vp, vp, vp]),
         "thm_export_elements": (i32, [vp, i64, i64, vp]),
         "thm_time_spmv": (i32, [vp, i32, i32, dp, dp, vp]),
+        "thm_time_spmv_batch": (i32, [vp, i32, i32, i32, dp, dp, vp]),
         "thm_time_precond": (i32, [vp, i32, i32, dp, dp, ctypes.POINTER(i32), vp]),
         "thm_set_spmv_variant": (i32, [vp, i32, i32]),
         "thm_apply_precond_full": (i32, [vp, i32, i32, vp, vp, vp]),
@@ -332,6 +333,15 @@ def thm_time_spmv(system, precision=THM_FP64, reps=20, stream=None):
     by = ctypes.c_double()
     _check(_lib.thm_time_spmv(system.handle, int(precision), int(reps), ctypes.byref(ms), ctypes.byref(by),
                               _stream(stream)))
+    return ms.value, by.value
+
+
+def thm_time_spmv_batch(system, precision=THM_FP64, variant=-1, reps=20, stream=None):
+    """(ms, algorithmic bytes) of one SpMV over the DDM's subdomain batch (after a DDM solve)."""
+    ms = ctypes.c_double()
+    by = ctypes.c_double()
+    _check(_lib.thm_time_spmv_batch(system.handle, int(precision), int(variant), int(reps), ctypes.byref(ms),
+                                    ctypes.byref(by), _stream(stream)))
     return ms.value, by.value
 
 

@@ -309,6 +309,7 @@ void Ctx::build_groups() {
         G.crow = sgcrow.p + coff[g];
     }
     sgroups.upload(h, st);
+    hgroups = h;
     gsched.build(waves, 4, st);
     THM_HIP(hipStreamSynchronize(st));
 }

@@ -167,6 +167,7 @@ struct Ctx {
     int lpr64 = 81, lpr32 = 81;  // SpMV variants (10 * lanes_per_row + unroll, or a SELL code)
     // groups of systems with the same K for the grouped SELL product (SPMV_SELL_GROUP)
     DBuf<SpmvGroup> sgroups;
+    std::vector<SpmvGroup> hgroups;  // host copy (crow points to device memory)
     DBuf<uint8_t> sgcrow;
     Sched gsched;
     int ngroups = 0;

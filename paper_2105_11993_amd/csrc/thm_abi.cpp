@@ -1228,6 +1228,55 @@ thm_status thm_time_spmv(thm_system *sys, int32_t precision, int32_t reps, doubl
     });
 }
 
+thm_status thm_time_spmv_batch(thm_system *sys, int32_t precision, int32_t variant, int32_t reps, double *ms_out,
+                               double *bytes_out, void *stream) {
+    return guard([&] {
+        if (!sys || !ms_out || reps < 1) fail(THM_EINVAL, "bad arguments");
+        if (precision != THM_FP64 && precision != THM_FP32_IR) fail(THM_EINVAL, "unknown precision");
+        if (!sys->ddm || !sys->ddm->inner) fail(THM_EINVAL, "no subdomain batch yet: run thm_ddm_solve first");
+        static const int known[] = {21, 41, 81, 161, 321, 641, 24, 44, 84, 164, 324, THM_SPMV_SELL,
+                                    THM_SPMV_SELL_GROUP};
+        bool ok = variant == -1;
+        for (int k : known) ok = ok || k == variant;
+        if (!ok) fail(THM_EINVAL, "unknown SpMV variant");
+        Ctx &c = *sys->ddm->inner;
+        const bool f32 = precision == THM_FP32_IR;
+        const int v = variant >= 0 ? variant : (f32 ? c.lpr32 : c.lpr64);
+        hipStream_t us = (hipStream_t)stream;
+        stream_join(us, c.st);
+        c.ops32(1.f, false);  // allocates the FP32 slots on first use
+        hipEvent_t e0, e1;
+        THM_HIP(hipEventCreate(&e0));
+        THM_HIP(hipEventCreate(&e1));
+        auto once = [&] {
+            if (f32) c.spmv<float>(v, nullptr, c.x32.p, c.b32.p, nullptr, 1.f);
+            else c.spmv<double>(v, nullptr, c.x64.p, c.r64.p, nullptr, 1.f);
+        };
+        once();
+        THM_HIP(hipEventRecord(e0, c.st));
+        for (int r = 0; r < reps; ++r) once();
+        THM_HIP(hipEventRecord(e1, c.st));
+        THM_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        THM_HIP(hipEventElapsedTime(&ms, e0, e1));
+        THM_HIP(hipEventDestroy(e0));
+        THM_HIP(hipEventDestroy(e1));
+        *ms_out = ms / reps;
+        if (bytes_out) {
+            const double w = f32 ? 4.0 : 8.0;
+            double by = 0.0;
+            for (const SpmvGroup &g : c.hgroups) {  // each distinct K once, with its row pointers
+                const thm_system &R = *c.sys[g.rep];
+                by += (w + 4.0) * (double)R.K.col.size() + 4.0 * (double)(R.n + 1);
+            }
+            for (const thm_system *m : c.sys)  // per system: C, its row pointers, x read and y written
+                by += (w + 4.0) * (double)m->C.col.size() + 4.0 * (double)(m->n + 1) + 2.0 * 2.0 * m->n * w;
+            *bytes_out = by;
+        }
+        stream_join(c.st, us);
+    });
+}
+
 static_assert(THM_SPMV_SELL == thm::SPMV_SELL && THM_SPMV_SELL_GROUP == thm::SPMV_SELL_GROUP,
               "SpMV variant codes of the header and the kernels differ");
 

@@ -67,3 +67,47 @@ def test_grouped_product_with_distinct_subdomains(thm):
     assert st["status"] == 0
     Eg = system.solve_lu(system.assemble(problem(d)))
     assert rel(E, Eg) <= 1e-9
+
+
+def test_batched_spmv_timing_counts_each_distinct_k_once(thm):
+    """thm_time_spmv_batch needs the DDM's subdomain batch; its algorithmic bytes are the
+    same for every variant: the two distinct K of the homogeneous 4x4 partition once each,
+    and per subdomain its C, row pointers, x read once and y written once.  The counts are
+    the stored (structural) patterns, taken from the oracle's subdomain meshes: K has one
+    entry per pair of DoFs that share a cell, and C (2D, degree p) p + 1 entries in each
+    row it touches, since an edge's trace DoFs couple only to each other.  The oracle's
+    own matrices drop the entries that Legendre orthogonality makes exactly zero."""
+    import scipy.sparse as sps
+    from oracle import ddm
+    d = dict(workloads.c2(32))
+    print("case c2-32 batched spmv timing", flush=True)
+    S = thm.thm_assemble(d)
+    with pytest.raises(thm.ThmError):
+        thm.thm_time_spmv_batch(S)
+    thm.thm_ddm_solve(S, thm.default_opts(rtol=1e-8, inner_rtol=1e-10))
+    subs = ddm.DDM(problem(d)).subs
+
+    def k_pattern(s):
+        T = s.mesh.table()
+        r = np.repeat(T, T.shape[1], axis=1).ravel()
+        c = np.tile(T, (1, T.shape[1])).ravel()
+        return sps.coo_matrix((np.ones(r.size), (r, c)), shape=(s.n, s.n)).tocsr().nnz
+
+    def c_pattern(s):
+        return (d["p"] + 1) * int((np.diff(s.C.tocsr().indptr) > 0).sum())
+
+    nk = {k_pattern(s) for s in subs}
+    assert len(nk) == 1
+    nk = nk.pop()
+    assert nk > subs[0].K.nnz  # the orthogonality zeros the oracle's sparse sums drop
+    for prec, w in ((thm.THM_FP64, 8), (thm.THM_FP32_IR, 4)):
+        ref = 2 * ((w + 4) * nk + 4 * (subs[0].n + 1))
+        ref += sum((w + 4) * c_pattern(s) + 4 * (s.n + 1) + 4 * s.n * w for s in subs)
+        for v in (thm.THM_SPMV_SELL, thm.THM_SPMV_SELL_GROUP):
+            ms, by = thm.thm_time_spmv_batch(S, prec, v, reps=3)
+            print(f"  prec {prec} variant {v}: {ms * 1e3:.1f} us, {by / 1e6:.3f} MB (oracle sizes {ref / 1e6:.3f})",
+                  flush=True)
+            assert ms > 0.0
+            assert by == pytest.approx(ref, rel=1e-12)
+    with pytest.raises(thm.ThmError):
+        thm.thm_time_spmv_batch(S, thm.THM_FP64, 17)
