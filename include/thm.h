@@ -104,7 +104,7 @@ typedef struct {
     int32_t max_refine;      /* refinement steps for THM_FP32_IR (30) */
     int32_t krylov;          /* thm_krylov (THM_KRYLOV_COMPLEX) */
     int32_t relax_inner;     /* DDM interface GMRES only: 1 = before each outer operator application the
-                                subdomain tolerance is max(inner_rtol, min(1e-4, 1e-2 rtol / r)) with r the
+                                subdomain tolerance is max(inner_rtol, min(1e-2, 3e-2 rtol / r)) with r the
                                 outer GMRES's current relative residual estimate (inexact Krylov
                                 relaxation: late outer steps tolerate less accurate subdomain solves; the
                                 returned field still meets rtol in the global FP64 residual). Suited to outer
