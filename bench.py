@@ -178,7 +178,7 @@ def measured_traffic(algorithmic_bytes_per_launch):
 
 
 def run_batch(args, thm, torch, workloads):
-    """C4: many independent 2D problems of uneven size (mesh, degree, w, incidence drawn
+    """Many independent 2D problems of uneven size (mesh, degree, w, incidence drawn
     from seed 4) solved to 1e-8 as one batched launch sequence, against the same problems
     solved one at a time in plain FP64."""
     specs = workloads.c4(args.count, scale=args.scale)

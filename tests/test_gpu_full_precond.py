@@ -81,7 +81,7 @@ def test_full_preconditioner_inverts_the_system(thm, d):
 
 
 def test_full_preconditioner_on_subdomain_shape(thm):
-    """The 64 x 64, degree-2 square of one C2 subdomain (576 boundary DoFs carry C): the
+    """The 64 x 64, degree-2 square of one subdomain of the 4x4-split 256x256 square (576 boundary DoFs carry C): the
     correction inverts K + iC to FP64 rounding and to FP32 accuracy in FP32."""
     import torch
     d = _randomize(spec(2, 64, 2, 50.0), 42)

@@ -171,7 +171,7 @@ def test_both_krylov_scalar_modes_match_lu(thm, krylov):
 
 
 def test_preconditioner_on_subdomain_shape(thm):
-    """A 64x64, degree-2 square (the shape of one C2 subdomain: 65 layers of 387 skeleton
+    """A 64x64, degree-2 square (the shape of one subdomain of the 4x4-split 256x256 square: 65 layers of 387 skeleton
     DoFs, three cyclic-reduction levels and a dense last system of 9 blocks): the MFMA
     apply inverts K exactly in FP64, to FP32 accuracy in FP32, and is bitwise
     reproducible."""
