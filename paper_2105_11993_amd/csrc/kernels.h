@@ -146,11 +146,20 @@ void launch_zero_flagged(const Batch &B, const uint8_t *const *dirs, T *x, hipSt
 
 // ---- preconditioner (kernels_prec.hip)
 // Per-system preconditioner description for batched application.
+// Skeleton work vectors of the apply (ws, ys): the members of a factor group share one
+// region of 8-position chunks.  Chunk q holds, for every padded member column of the group
+// (member j: real part in column 2j, imaginary part in column 2j + 1), its values at positions
+// 8q .. 8q + 7, so a chunk is cs = 16 x (padded members) scalars.  A member column's value at
+// position p lies wv_pos(p, cs) after the column's start, and the imaginary column starts 8
+// after the real one.
+__host__ __device__ inline int64_t wv_pos(int64_t p, int64_t cs) { return (p >> 3) * cs + (p & 7); }
+
 struct PrecDesc {
     int64_t n;                 // complex DoFs
     int64_t n_skel;            // skeleton DoFs
     int64_t cell_off;          // first interior DoF
-    int64_t sp;                // planar half-stride of the skeleton work vectors (re block, then im block)
+    int64_t sp;                // padded skeleton length (positions 0 .. sp - 1, a multiple of 8)
+    int64_t cs;                // chunk stride of the system's factor group (see wv_pos)
     int32_t n_cells, n_loc, n_int, ne, nlayers;
     const int32_t *cell_dofs;  // n_cells * n_loc
     const int32_t *skel_dof;   // skeleton position -> global DoF
@@ -185,7 +194,8 @@ struct BcrTask {
     int32_t seg_src[SEGMAX];   // 0 = ws (reduced RHS), 1 = ys (solution)
     int64_t seg_off[SEGMAX];   // padded position of the segment in a member's work vector
     int64_t out_off;           // padded position of the output block
-    int64_t sp;                // planar half-stride of the group's work vectors
+    int64_t gbase;             // start of the group's region in the work vectors
+    int64_t cs;                // its chunk stride (see wv_pos)
     // per 8-column chunk kc (ld / 8 entries): 2 (p - 8 kc) + src, where p is the position
     // of column 8 kc in a member's work vector and src selects ws (0) or ys (1); chunks
     // past the padded width repeat the last chunk of the last segment (zero in M)
@@ -217,7 +227,7 @@ struct PrecPhase {
 struct PrecBatch {
     int ns = 0;
     DBuf<PrecDesc> d64, d32;
-    DBuf<int64_t> soff;            // scalar offset of each system's skeleton vector
+    DBuf<int64_t> soff;            // start of each system's real column (group start + 16 j)
     int64_t Stot = 0;              // scalars per skeleton slot
     Sched skel;                    // 256 skeleton entries per block
     Sched dofs;                    // 256 DoFs per block
@@ -225,7 +235,6 @@ struct PrecBatch {
     DBuf<int64_t> toff;            // complex offset of each system's per-cell condensation terms
     int64_t Ttot = 0;              // complex entries of all condensation terms
     DBuf<int32_t> memb_ptr, memb;  // factor group -> member systems
-    DBuf<int64_t> msoff;           // soff of each entry of memb
     std::vector<PrecPhase> phases; // forward levels, top, backward levels
 };
 

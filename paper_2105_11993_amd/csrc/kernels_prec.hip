@@ -325,7 +325,7 @@ __global__ void __launch_bounds__(256) k_cond_fwd(const PrecDesc *__restrict__ p
     if (t >= d.n_skel) return;
     const T2 *r = reinterpret_cast<const T2 *>(rb + off[s]);
     const T2 *tw = reinterpret_cast<const T2 *>(twb) + toff[s];
-    T *ws = wsb + soff[s];
+    T *ws = wsb + soff[s];  // the system's real column; the imaginary one starts 8 later
     T2 acc = r[d.skel_dof[t]];
     if (d.n_int > 0)
         for (int32_t e = d.cond_ptr[t]; e < d.cond_ptr[t + 1]; ++e) {
@@ -333,9 +333,9 @@ __global__ void __launch_bounds__(256) k_cond_fwd(const PrecDesc *__restrict__ p
             acc.x -= v.x;
             acc.y -= v.y;
         }
-    const int32_t p = d.skel_pos[t];
-    ws[p] = acc.x;
-    ws[d.sp + p] = acc.y;
+    T *wp = ws + wv_pos(d.skel_pos[t], d.cs);
+    wp[0] = acc.x;
+    wp[8] = acc.y;
 }
 
 // ------------------------------------------------------------------ cyclic-reduction apply (MFMA)
@@ -410,19 +410,20 @@ struct BcrStep {
 };
 
 // Loads of one step; branch-free so that the next step's loads stay in flight while
-// the current step's MFMAs run.  Lanes of absent members read the chunk's first
-// member (their output columns are never stored).  A piece of X lies in one 8-column
-// chunk, whose table entry gives its position in the work vector.
+// the current step's MFMAs run.  Lanes of absent members read the group's zero padding
+// columns (their output columns are never stored).  A piece of X lies in one 8-column
+// chunk, whose table entry gives its position in the work vector; the 16 lanes of a lane
+// group read 16 adjacent member columns of one chunk, a contiguous run.
 template <class T, int NNT>
-__device__ __forceinline__ void bcr_fetch_b(BcrStep<T, NNT> &o, const int64_t (&bbase)[NNT], int k, const T *wsb,
-                                            const T *ysb) {
+__device__ __forceinline__ void bcr_fetch_b(BcrStep<T, NNT> &o, const int64_t (&bbase)[NNT], int64_t cs, int k,
+                                            const T *wsb, const T *ysb) {
     const int g = (threadIdx.x >> 4) & 3;
 #pragma unroll
     for (int h = 0; h < 8 / bcr_per<T>(); ++h) {
         const int c = k + bcr_col<T>(g, h * bcr_per<T>());
         const int32_t e = bcr_tab[c >> 3];
         const T *src = (e & 1) ? ysb : wsb;
-        const int64_t pos = (int64_t)(e >> 1) + c;
+        const int64_t pos = wv_pos((int64_t)(e >> 1) + c, cs);  // a piece never crosses a chunk
 #pragma unroll
         for (int nt = 0; nt < NNT; ++nt) load_piece(src + bbase[nt] + pos, o.b[nt], h);
     }
@@ -450,11 +451,11 @@ __device__ __forceinline__ void bcr_fetch_a(const T *A, T (&v)[8]) {
 
 template <class T, int WPB, int NNT>
 __device__ __forceinline__ void bcr_fetch(BcrStep<T, NNT> &o, const BcrShared<T, WPB> &sh,
-                                          const int64_t (&bbase)[NNT], const T *A0, const T *A1, int k,
-                                          const T *wsb, const T *ysb) {
+                                          const int64_t (&bbase)[NNT], int64_t cs, const T *A0, const T *A1,
+                                          int k, const T *wsb, const T *ysb) {
     bcr_fetch_a(A0 + (int64_t)BCR_RT * k, o.a0);  // step k / BCR_KS of the row tile
     bcr_fetch_a(A1 + (int64_t)BCR_RT * k, o.a1);
-    bcr_fetch_b(o, bbase, k, wsb, ysb);
+    bcr_fetch_b(o, bbase, cs, k, wsb, ysb);
 }
 
 template <class T, int NNT>
@@ -470,9 +471,8 @@ __device__ __forceinline__ void bcr_mma(const BcrStep<T, NNT> &o, typename Mfma<
 
 template <class T, int WPB, int NNT>
 __device__ __forceinline__ void bcr_tile(const BcrTask &tk, BcrShared<T, WPB> &sh, int row0, int mb, int m1,
-                                         const int32_t *__restrict__ memb, const int64_t *__restrict__ msoff,
-                                         const int32_t *__restrict__ mask, T *__restrict__ wsb,
-                                         T *__restrict__ ysb) {
+                                         const int32_t *__restrict__ memb, const int32_t *__restrict__ mask,
+                                         T *__restrict__ wsb, T *__restrict__ ysb) {
     using V4 = typename Mfma<T>::v4;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i16 = lane & 15, g = lane >> 4;
@@ -481,12 +481,11 @@ __device__ __forceinline__ void bcr_tile(const BcrTask &tk, BcrShared<T, WPB> &s
     // lane's values of m tile mt, step k, start at row0 ld + BCR_RT k + 512 mt + P lane
     const T *A0 = M + (int64_t)row0 * tk.ld + bcr_per<T>() * lane;
     const T *A1 = A0 + 16 * BCR_KS;
+    // start of this lane's member column (member mi - mbeg of the group, re or im)
     int64_t bbase[NNT];
 #pragma unroll
-    for (int nt = 0; nt < NNT; ++nt) {
-        const int mi = mb + 8 * nt + (i16 >> 1);
-        bbase[nt] = msoff[mi < m1 ? mi : mb] + (i16 & 1) * tk.sp;
-    }
+    for (int nt = 0; nt < NNT; ++nt)
+        bbase[nt] = tk.gbase + 16 * (int64_t)(mb + 8 * nt + (i16 >> 1) - tk.mbeg) + 8 * (i16 & 1);
     V4 acc[2][NNT];
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt)
@@ -516,7 +515,8 @@ __device__ __forceinline__ void bcr_tile(const BcrTask &tk, BcrShared<T, WPB> &s
             const int n = o / BCR_RT, r = o % BCR_RT;
             const int mi = mb + (n >> 1);
             if (o < NOUT && row0 + r < tk.rows && mi < m1)
-                sh.yold[o] = ((tk.out_dst ? ysb : wsb) + msoff[mi] + (n & 1) * tk.sp + tk.out_off)[row0 + r];
+                sh.yold[o] = (tk.out_dst ? ysb : wsb)[tk.gbase + 16 * (int64_t)(mi - tk.mbeg) + 8 * (n & 1) +
+                                                      wv_pos(tk.out_off + row0 + r, tk.cs)];
         }
     }
     for (int kc = threadIdx.x; kc < (tk.ld >> 3); kc += blockDim.x) bcr_tab[kc] = tk.tab[kc];
@@ -529,13 +529,13 @@ __device__ __forceinline__ void bcr_tile(const BcrTask &tk, BcrShared<T, WPB> &s
         // last step's addresses; the scheduling barriers keep each prefetch ahead of the
         // MFMAs it overlaps.
         const int klast = kbeg + (nst - 1) * BCR_KS;
-        bcr_fetch_b(p, bbase, kbeg, wsb, ysb);
+        bcr_fetch_b(p, bbase, tk.cs, kbeg, wsb, ysb);
         int st = 0;
         for (; st + 2 <= nst; st += 2) {
-            bcr_fetch<T, WPB, NNT>(q, sh, bbase, A0, A1, kbeg + (st + 1) * BCR_KS, wsb, ysb);
+            bcr_fetch<T, WPB, NNT>(q, sh, bbase, tk.cs, A0, A1, kbeg + (st + 1) * BCR_KS, wsb, ysb);
             __builtin_amdgcn_sched_barrier(0);
             bcr_mma(p, acc);
-            bcr_fetch<T, WPB, NNT>(p, sh, bbase, A0, A1, min(kbeg + (st + 2) * BCR_KS, klast), wsb, ysb);
+            bcr_fetch<T, WPB, NNT>(p, sh, bbase, tk.cs, A0, A1, min(kbeg + (st + 2) * BCR_KS, klast), wsb, ysb);
             __builtin_amdgcn_sched_barrier(0);
             bcr_mma(q, acc);
         }
@@ -578,7 +578,8 @@ __device__ __forceinline__ void bcr_tile(const BcrTask &tk, BcrShared<T, WPB> &s
         T v = 0;
 #pragma unroll
         for (int w = 0; w < H; ++w) v += sh.red[w][n][r];
-        T *y = (tk.out_dst ? ysb : wsb) + msoff[mi] + (n & 1) * tk.sp + tk.out_off + row0 + r;
+        T *y = (tk.out_dst ? ysb : wsb) + tk.gbase + 16 * (int64_t)(mi - tk.mbeg) + 8 * (n & 1) +
+               wv_pos(tk.out_off + row0 + r, tk.cs);
         *y = tk.subtract ? sh.yold[o] - v : v;
     }
 }
@@ -591,7 +592,6 @@ template <class T, int WPB>
 __global__ void __launch_bounds__(64 * WPB, BcrOcc<T>::v) k_bcr_mfma(const BcrTask *__restrict__ tasks,
                                                        const int32_t *__restrict__ blkoff, int ntasks,
                                                        const int32_t *__restrict__ memb,
-                                                       const int64_t *__restrict__ msoff,
                                                        const int32_t *__restrict__ mask, T *__restrict__ wsb,
                                                        T *__restrict__ ysb) {
     __shared__ BcrShared<T, WPB> sh;
@@ -608,9 +608,9 @@ __global__ void __launch_bounds__(64 * WPB, BcrOcc<T>::v) k_bcr_mfma(const BcrTa
     const int m1 = tk.mend;
     const int mb = tk.mbeg + mchunk * 8 * tk.nnt;
     if (tk.nnt == 1)
-        bcr_tile<T, WPB, 1>(tk, sh, rt * BCR_RT, mb, m1, memb, msoff, mask, wsb, ysb);
+        bcr_tile<T, WPB, 1>(tk, sh, rt * BCR_RT, mb, m1, memb, mask, wsb, ysb);
     else
-        bcr_tile<T, WPB, 2>(tk, sh, rt * BCR_RT, mb, m1, memb, msoff, mask, wsb, ysb);
+        bcr_tile<T, WPB, 2>(tk, sh, rt * BCR_RT, mb, m1, memb, mask, wsb, ysb);
 }
 
 // x[g] = ys[pos(g)] on skeleton DoFs; interiors: x_i = Kii^{-1} r_i - F^T x_e.
@@ -628,8 +628,8 @@ __global__ void __launch_bounds__(256) k_cond_bwd(const PrecDesc *__restrict__ p
     const T *ys = ysb + soff[s];
     T2 *x = reinterpret_cast<T2 *>(xb + off[s]);
     if (g < d.cell_off) {
-        const int32_t p = d.dof_pos[g];
-        x[g] = T2{ys[p], ys[d.sp + p]};
+        const T *yp = ys + wv_pos(d.dof_pos[g], d.cs);
+        x[g] = T2{yp[0], yp[8]};
         return;
     }
     const T2 *r = reinterpret_cast<const T2 *>(rb + off[s]);
@@ -649,9 +649,9 @@ __global__ void __launch_bounds__(256) k_cond_bwd(const PrecDesc *__restrict__ p
 #pragma unroll 4
     for (int le = 0; le < d.ne; ++le) {
         const T f = F[le * d.n_int + m];
-        const int32_t p = cp[le];
-        acc.x -= f * ys[p];
-        acc.y -= f * ys[d.sp + p];
+        const T *yp = ys + wv_pos(cp[le], d.cs);
+        acc.x -= f * yp[0];
+        acc.y -= f * yp[8];
     }
     x[g] = acc;
 }
@@ -663,7 +663,7 @@ void launch_bcr_phases(const PrecBatch &P, const int32_t *mask, T *ws, T *ys, hi
         const int nb = ph.sched[prec].nblocks;
         if (!nb) continue;
         k_bcr_mfma<T, BCR_WPB><<<nb, 64 * BCR_WPB, sizeof(int32_t) * (ph.max_ld / 8), st>>>(
-            ph.tasks[prec].p, ph.sched[prec].blkoff.p, ph.ntasks, P.memb.p, P.msoff.p, mask, ws, ys);
+            ph.tasks[prec].p, ph.sched[prec].blkoff.p, ph.ntasks, P.memb.p, mask, ws, ys);
     }
     THM_HIP(hipGetLastError());
 }

@@ -341,7 +341,6 @@ void Ctx::build_prec() {
     // factor groups in order of first appearance
     std::vector<Factor *> groups;
     std::vector<std::vector<int32_t>> members;
-    int64_t so = 0;
     for (int i = 0; i < ns; ++i) {
         thm_system &S = *sys[i];
         Factor &f = *S.fac;
@@ -379,9 +378,28 @@ void Ctx::build_prec() {
         p32[i].kiinv = f.kiinv32.p;
         p32[i].F = f.F32.p;
         p32[i].FT = f.FT32.p;
-        soff[i] = so;
-        so += 2 * S.L.n_skel_pad;  // planar: real block, then imaginary block
+    }
+    // Work vectors: one region per factor group, its members' columns interleaved by
+    // 8-position chunks (see wv_pos); the member count is padded to the 8 or 16 columns
+    // pairs of one block's n tiles, so absent members read zero columns.
+    std::vector<int64_t> gbase(groups.size()), gcs(groups.size());
+    int64_t so = 0;
+    for (size_t g = 0; g < groups.size(); ++g) {
+        const int nm = (int)members[g].size();
+        const int nnt = nm > 8 ? 2 : 1;  // the same split as the tasks below
+        const int64_t nmp = (int64_t)((nm + 8 * nnt - 1) / (8 * nnt)) * 8 * nnt;
+        const int64_t sp = groups[g]->sp;
+        if (sp % 8) fail(THM_EINVAL, "skeleton length not padded to 8");
+        gcs[g] = 16 * nmp;
+        gbase[g] = so;
+        so += sp / 8 * gcs[g];
         so = (so + 63) & ~int64_t(63);
+        for (int j = 0; j < nm; ++j) {
+            const int i = members[g][j];
+            if (p64[i].sp != sp) fail(THM_EINVAL, "members of a factor group differ in skeleton length");
+            soff[i] = gbase[g] + 16 * (int64_t)j;
+            p64[i].cs = p32[i].cs = gcs[g];
+        }
     }
     P.ns = ns;
     P.d64.upload(p64, st);
@@ -412,9 +430,6 @@ void Ctx::build_prec() {
         }
         P.memb_ptr.upload(mp, st);
         P.memb.upload(mm, st);
-        std::vector<int64_t> ms(mm.size());
-        for (size_t i = 0; i < mm.size(); ++i) ms[i] = soff.at(mm[i]);
-        P.msoff.upload(ms, st);
     }
     // cyclic-reduction phases: forward levels, last blocks, backward levels
     int nlev = 0;
@@ -440,7 +455,9 @@ void Ctx::build_prec() {
         t.out_off = f.pboff[b.layer];
         t.out_dst = b.out_dst;
         t.subtract = b.subtract;
-        t.sp = f.sp;
+        t.gbase = gbase[g];
+        t.cs = gcs[g];
+        if (t.out_off % 8 || t.out_off + b.rows > f.sp) fail(THM_EINVAL, "apply output outside the work vectors");
         return t;
     };
     P.phases.clear();
@@ -478,6 +495,12 @@ void Ctx::build_prec() {
                 ph.max_ld = std::max(ph.max_ld, t.ld);
                 at.push_back((int64_t)all.size());
                 bcr_chunk_table(t, one);
+                // every chunk the kernel reads lies inside the group's positions
+                const int64_t sp = groups[t.group]->sp;
+                for (size_t kc = 0; kc < one.size(); ++kc) {
+                    const int64_t p0 = (int64_t)(one[kc] >> 1) + 8 * (int64_t)kc;
+                    if (p0 < 0 || p0 % 8 || p0 + 8 > sp) fail(THM_EINVAL, "apply input outside the work vectors");
+                }
                 all.insert(all.end(), one.begin(), one.end());
             }
             ph.tab.upload(all, st);
