@@ -309,8 +309,8 @@ __global__ void __launch_bounds__(256) k_cond_fr(const PrecDesc *__restrict__ pd
     reinterpret_cast<T2 *>(twb)[toff[s] + e] = acc;
 }
 
-// ws[t] = r[skel_dof[t]] - sum over the cells c of t of (F_c r_int(c))[local t], stored
-// planar at the padded position: real parts in ws[0, sp), imaginary parts in ws[sp, 2 sp).
+// ws[t] = r[skel_dof[t]] - sum over the cells c of t of (F_c r_int(c))[local t], stored at
+// the padded position of the system's member columns (see wv_pos).
 template <class T>
 __global__ void __launch_bounds__(256) k_cond_fwd(const PrecDesc *__restrict__ pd, const int64_t *__restrict__ off,
                                                   const int64_t *__restrict__ soff, const int64_t *__restrict__ toff,

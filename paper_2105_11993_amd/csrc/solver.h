@@ -19,7 +19,7 @@ struct Factor {
     int n_int = 0, ne = 0;
     int64_t n_cells = 0;
     std::vector<int64_t> pboff;  // padded layer offsets of the skeleton work vectors
-    int64_t sp = 0;              // padded skeleton length (one planar half)
+    int64_t sp = 0;              // padded skeleton length (positions per member column)
     DBuf<double> kiinv, F, FT;     // kiinv stored transposed per cell after setup (see PrecDesc)
     DBuf<float> kiinv32, F32, FT32;
     DBuf<double> mat;            // apply matrices during setup (rows x cols, segments packed)
