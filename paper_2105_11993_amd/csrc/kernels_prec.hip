@@ -410,8 +410,8 @@ struct BcrStep {
 };
 
 // Loads of one step; branch-free so that the next step's loads stay in flight while
-// the current step's MFMAs run.  Lanes of absent members read the group's zero padding
-// columns (their output columns are never stored).  A piece of X lies in one 8-column
+// the current step's MFMAs run.  Lanes of absent members read the chunk's first member
+// (their output columns are never stored).  A piece of X lies in one 8-column
 // chunk, whose table entry gives its position in the work vector; the 16 lanes of a lane
 // group read 16 adjacent member columns of one chunk, a contiguous run.
 template <class T, int NNT>
@@ -481,11 +481,14 @@ __device__ __forceinline__ void bcr_tile(const BcrTask &tk, BcrShared<T, WPB> &s
     // lane's values of m tile mt, step k, start at row0 ld + BCR_RT k + 512 mt + P lane
     const T *A0 = M + (int64_t)row0 * tk.ld + bcr_per<T>() * lane;
     const T *A1 = A0 + 16 * BCR_KS;
-    // start of this lane's member column (member mi - mbeg of the group, re or im)
+    // start of this lane's member column (member mi - mbeg of the group, re or im); lanes of
+    // absent members read the chunk's first member, whose lines the other lanes fetch anyway
     int64_t bbase[NNT];
 #pragma unroll
-    for (int nt = 0; nt < NNT; ++nt)
-        bbase[nt] = tk.gbase + 16 * (int64_t)(mb + 8 * nt + (i16 >> 1) - tk.mbeg) + 8 * (i16 & 1);
+    for (int nt = 0; nt < NNT; ++nt) {
+        const int mi = mb + 8 * nt + (i16 >> 1);
+        bbase[nt] = tk.gbase + 16 * (int64_t)((mi < m1 ? mi : mb) - tk.mbeg) + 8 * (i16 & 1);
+    }
     V4 acc[2][NNT];
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt)

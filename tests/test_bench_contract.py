@@ -4,7 +4,6 @@ source is the one the counters were taken on."""
 import importlib.util
 import json
 import os
-import shutil
 import subprocess
 import sys
 
@@ -27,16 +26,21 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_traffic_follows_the_kernel_source(tmp_path):
+    """A traffic record is used only for the kernel source whose SHA-256 it carries."""
+    import hashlib
     bench = _bench_module()
-    rec = json.load(open(os.path.join(ROOT, "profiles", "k_bcr_mfma_c2_traffic.json")))
-    # the committed record matches the committed source
-    assert bench.measured_traffic(63.5e6) == rec["hbm_bytes_per_launch"]
-    # a copy of the tree whose kernel source differs by one byte gets no traffic figure
+    src = open(os.path.join(ROOT, "paper_2105_11993_amd", "csrc", "kernels_prec.hip"), "rb").read()
     (tmp_path / "profiles").mkdir()
-    shutil.copy(os.path.join(ROOT, "profiles", "k_bcr_mfma_c2_traffic.json"), tmp_path / "profiles")
     csrc = tmp_path / "paper_2105_11993_amd" / "csrc"
     csrc.mkdir(parents=True)
-    src = open(os.path.join(ROOT, "paper_2105_11993_amd", "csrc", "kernels_prec.hip"), "rb").read()
-    (csrc / "kernels_prec.hip").write_bytes(src + b"\n")
+    (csrc / "kernels_prec.hip").write_bytes(src)
+    rec = {"hbm_bytes_per_launch": 7.0e7, "kernels_prec_sha256": hashlib.sha256(src).hexdigest()}
+    (tmp_path / "profiles" / "k_bcr_mfma_c2_traffic.json").write_text(json.dumps(rec))
     bench.ROOT = str(tmp_path)
+    assert bench.measured_traffic(63.5e6) == 7.0e7
+    # the source differs by one byte: no traffic figure
+    (csrc / "kernels_prec.hip").write_bytes(src + b"\n")
+    assert bench.measured_traffic(63.5e6) is None
+    # no record at all: none either
+    (tmp_path / "profiles" / "k_bcr_mfma_c2_traffic.json").unlink()
     assert bench.measured_traffic(63.5e6) is None
