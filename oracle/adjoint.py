@@ -15,7 +15,6 @@ from dataclasses import replace
 
 import numpy as np
 import scipy.sparse as sp
-import scipy.sparse.linalg as spla
 
 from . import fe, system
 
@@ -70,11 +69,9 @@ def objective(sys, E, MT):
 def gradient(sys, E, MT):
     """Exact discrete dJ/dmu per cell by one adjoint (conjugate) solve."""
     F = sys.F
-    S = sys.S
     rhs = (MT @ E)[F]
-    lu = spla.splu(S[F][:, F].conj().tocsc())
     lam = np.zeros(sys.n, dtype=np.complex128)
-    lam[F] = lu.solve(rhs)
+    lam[F] = system.lu_factor(sys, conj=True)(rhs)
     T = sys.T
     Ec = E[T]
     Lc = lam[T]

@@ -22,7 +22,6 @@ consistent with each other):
 from dataclasses import dataclass, replace
 
 import numpy as np
-import scipy.sparse.linalg as spla
 
 from . import system
 from .gmres import gmres as _gmres
@@ -90,7 +89,7 @@ class DDM:
             assert (l2g >= 0).all()
             ls.gD = np.array([gD[g] for g in l2g[ls.D]], dtype=np.complex128)
             ls.extra["l2g"] = l2g
-            ls.extra["lu"] = spla.splu(ls.S[ls.F][:, ls.F].tocsc())
+            ls.extra["lu"] = system.lu_factor(ls)
             self.subs.append(ls)
         self.ifaces = []
         for s in range(nsub):
@@ -160,7 +159,7 @@ class DDM:
             rF = rhs[ls.F]
             if incident and len(ls.D):
                 rF = rF + ls.rhs_free()
-            EF = ls.extra["lu"].solve(rF)
+            EF = ls.extra["lu"](rF)
             E = np.zeros(ls.mesh.n_dofs, dtype=np.complex128)
             E[ls.F] = EF
             if incident:

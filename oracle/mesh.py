@@ -154,6 +154,29 @@ class BoxMesh:
         cells = self.side_cells(axis, side)
         return np.unique(T[np.ix_(cells, loc)].ravel())
 
+    def dof_positions2(self):
+        """(n_dofs, dim) int64: twice the position, in cells, of the entity carrying each DoF
+        (an x-edge (i, j, k) sits at (2i+1, 2j, 2k), an x-face at (2i, 2j+1, 2k+1), a cell at
+        (2i+1, 2j+1, 2k+1)).  Used only to order the unknowns of the sparse LU."""
+        d, pe, n = self.dim, self.p + 1, self.n
+
+        def grid(shape):  # entity indices, x fastest, as rows (i, j[, k])
+            return np.indices(tuple(reversed(shape))).reshape(len(shape), -1)[::-1].T
+
+        X = np.zeros((self.n_dofs, d), dtype=np.int64)
+        for a in range(d):
+            g = 2 * grid([n[b] + (0 if b == a else 1) for b in range(d)])
+            g[:, a] += 1
+            X[self.edge_off[a]:self.edge_off[a] + len(g) * pe] = np.repeat(g, pe, axis=0)
+        if d == 3:
+            for a in range(3):
+                g = 2 * grid([n[b] + (1 if b == a else 0) for b in range(3)]) + 1
+                g[:, a] -= 1
+                X[self.face_off[a]:self.face_off[a] + len(g) * self.pf] = np.repeat(g, self.pf, axis=0)
+        g = 2 * grid(list(n)) + 1
+        X[self.cell_off:] = np.repeat(g, self.pi, axis=0)
+        return X
+
     def table(self):
         if not hasattr(self, "_T"):
             self._T = self.cell_dofs()

@@ -193,12 +193,56 @@ def assemble(prob, extra_inf_sides=()):
     return System(prob, mesh, T, mu, Mh, Ah, K.tocsr(), M, A, Minf.tocsr(), C.tocsr(), D, gD, F)
 
 
+def nested_dissection(mesh, dofs):
+    """Fill-reducing order of `dofs` for the sparse LU (an ordering only: the solve is the same
+    linear system).  The box of cells is cut in halves along its longest axis at a mesh plane;
+    the DoFs on entities inside that plane separate the two halves (no cell holds DoFs of both),
+    so they are ordered after the two halves, each ordered the same way recursively."""
+    X = mesh.dof_positions2()[dofs]
+    out = []
+
+    def rec(idx, lo, hi):
+        span = (hi - lo) // 2
+        a = int(np.argmax(span))
+        if span[a] <= 1 or len(idx) < 64:
+            out.append(idx)
+            return
+        cut = lo[a] + 2 * (span[a] // 2)
+        c = X[idx, a]
+        hi1, lo2 = hi.copy(), lo.copy()
+        hi1[a] = lo2[a] = cut
+        rec(idx[c < cut], lo, hi1)
+        rec(idx[c > cut], lo2, hi)
+        out.append(idx[c == cut])
+
+    rec(np.arange(len(dofs)), np.zeros(mesh.dim, np.int64), 2 * np.asarray(mesh.n, np.int64))
+    perm = np.concatenate(out)
+    assert len(perm) == len(dofs)
+    return perm
+
+
+def lu_factor(sys, conj=False):
+    """SuperLU factorisation of S_FF (or conj(S_FF)) with the unknowns in nested-dissection
+    order (threshold partial pivoting, threshold 0.1).  Returns solve(rhs_F) -> x_F."""
+    perm = nested_dissection(sys.mesh, sys.F)
+    SFF = sys.S[sys.F][:, sys.F]
+    if conj:
+        SFF = SFF.conj()
+    lu = spla.splu(SFF[perm][:, perm].tocsc(), permc_spec="NATURAL", diag_pivot_thresh=0.1,
+                   options=dict(SymmetricMode=True))
+
+    def solve(b):
+        y = lu.solve(np.asarray(b, dtype=np.complex128)[perm])
+        x = np.empty_like(y)
+        x[perm] = y
+        return x
+
+    return solve
+
+
 def solve_lu(sys):
     """E = [S_FF^{-1}(-S_FD g_D); g_D] by sparse LU (SuperLU)."""
-    S = sys.S
-    SFF = S[sys.F][:, sys.F].tocsc()
-    EF = spla.splu(SFF).solve(sys.rhs_free())
-    return sys.full(EF)
+    return sys.full(lu_factor(sys)(sys.rhs_free()))
 
 
 def solve_dense(sys):

@@ -157,3 +157,30 @@ def test_counts_brute_force(dim, m, p):
 def test_counts_configs(dim, m, p, N, nnz):
     mesh = BoxMesh(dim, (m,) * dim, p=p)
     assert mesh.n_dofs == N and structural_nnz(mesh) == nnz
+
+
+@pytest.mark.parametrize("dim,m,p", [(2, 3, 1), (2, 4, 2), (3, 2, 1)])
+def test_relative_residual_exact_values(dim, m, p):
+    """Pins relative_residual (the oracle's check of the large timed runs) by values fixed
+    without it: the dense brute-force solution has residual at rounding level; E = 0 on the
+    free DoFs leaves all of f, so the ratio is exactly 1; E = (1 - t) E* leaves t f, so the
+    ratio is t; twice the solution leaves -f (ratio 1); and Dirichlet entries of the argument
+    are not read (the lift already carries g_D)."""
+    prob = Problem(dim=dim, n=(m,) * dim + (1,) * (3 - dim), p=p, omega=7.0, inc_faces=1,
+                   mu=np.linspace(1.0, 2.0, m ** dim))
+    s = system.assemble(prob)
+    Ed = system.solve_dense(s)
+    assert system.relative_residual(s, Ed) <= 1e-13
+    Z = Ed.copy()
+    Z[s.F] = 0.0
+    assert system.relative_residual(s, Z) == pytest.approx(1.0, abs=1e-15)
+    for t in (0.5, 1e-3, 1e-8):
+        Et = Ed.copy()
+        Et[s.F] *= (1.0 - t)
+        assert system.relative_residual(s, Et) == pytest.approx(t, rel=1e-6 if t < 1e-6 else 1e-10)
+    E2 = Ed.copy()
+    E2[s.F] *= 2.0
+    assert system.relative_residual(s, E2) == pytest.approx(1.0, rel=1e-10)
+    Eg = Ed.copy()
+    Eg[s.D] = 1e6 * (1 + 1j)
+    assert system.relative_residual(s, Eg) <= 1e-13
