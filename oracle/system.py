@@ -221,20 +221,39 @@ def nested_dissection(mesh, dofs):
     return perm
 
 
-def lu_factor(sys, conj=False):
+def lu_factor(sys, conj=False, refine=3):
     """SuperLU factorisation of S_FF (or conj(S_FF)) with the unknowns in nested-dissection
-    order (threshold partial pivoting, threshold 0.1).  Returns solve(rhs_F) -> x_F."""
+    order (threshold partial pivoting, threshold 0.1).  Returns solve(rhs_F) -> x_F: the LU
+    solution followed by up to `refine` steps of iterative refinement with the same factors
+    (x += LU^{-1}(b - S_FF x), while the residual keeps falling), so that ill-conditioned systems
+    (near-resonant cavities of the uneven batch) are still solved to rounding level rather than
+    to the accuracy of a threshold-pivoted LU."""
     perm = nested_dissection(sys.mesh, sys.F)
     SFF = sys.S[sys.F][:, sys.F]
     if conj:
         SFF = SFF.conj()
+    SFF = SFF.tocsr()
     lu = spla.splu(SFF[perm][:, perm].tocsc(), permc_spec="NATURAL", diag_pivot_thresh=0.1,
                    options=dict(SymmetricMode=True))
 
-    def solve(b):
-        y = lu.solve(np.asarray(b, dtype=np.complex128)[perm])
+    def lu_solve(b):
+        y = lu.solve(b[perm])
         x = np.empty_like(y)
         x[perm] = y
+        return x
+
+    def solve(b):
+        b = np.asarray(b, dtype=np.complex128)
+        x = lu_solve(b)
+        r = b - SFF @ x
+        rn = np.linalg.norm(r)
+        for _ in range(refine):
+            x1 = x + lu_solve(r)
+            r1 = b - SFF @ x1
+            rn1 = np.linalg.norm(r1)
+            if not rn1 < rn:
+                break
+            x, r, rn = x1, r1, rn1
         return x
 
     return solve
