@@ -65,6 +65,15 @@ typedef enum { THM_KRYLOV_COMPLEX = 0, THM_KRYLOV_REAL = 1 } thm_krylov;
  * Supported for r <= 4096 per subdomain (THM_EUNSUPPORTED above: the setup inverts the
  * dense 2r x 2r real form of M). */
 typedef enum { THM_PREC_BLOCK = 0, THM_PREC_FULL = 1 } thm_precond;
+/* How THM_FP32_IR refines (block preconditioner).  THM_IR_CLASSIC: FP64 residuals, each correction
+ * by one cycle of FP32 GMRES (FP32 operator, basis and factor); a step that does not halve a
+ * system's FP64 residual is undone and that system continues by GMRES-based refinement, as do
+ * its later solves in the same batch (until its matrices change).
+ * THM_IR_GMRES: GMRES-based refinement from the start (Carson and Higham's GMRES-IR: the
+ * correction is solved by FP64 GMRES -- FP64 operator, basis and Hessenberg -- preconditioned by
+ * the FP32 factor, so the factor's accuracy limits only the convergence rate).  Either way a
+ * system GMRES-IR leaves above rtol is finished by FP64 GMRES with the FP64 factor. */
+typedef enum { THM_IR_CLASSIC = 0, THM_IR_GMRES = 1 } thm_ir_mode;
 
 /* Problem statement (paper Sec. 2, eq. (1); partition eq. (5)).  Copied by thm_assemble. */
 typedef struct {
@@ -103,16 +112,17 @@ typedef struct {
     double ir_inner_rtol;    /* floor of the FP32 inner tolerance per refinement step (1e-6) */
     int32_t max_refine;      /* refinement steps for THM_FP32_IR (30) */
     int32_t krylov;          /* thm_krylov (THM_KRYLOV_COMPLEX) */
-    int32_t relax_inner;     /* DDM interface GMRES only: 1 = before each outer operator application the
-                                subdomain tolerance is max(inner_rtol, min(1e-2, 3e-2 rtol / r)) with r the
-                                outer GMRES's current relative residual estimate (inexact Krylov
-                                relaxation: late outer steps tolerate less accurate subdomain solves; the
-                                returned field still meets rtol in the global FP64 residual). Suited to outer
-                                iterations that converge in few steps: where the outer operator is ill
-                                conditioned the outer residual estimate can stall above rtol, and the outer
-                                GMRES then runs to max_outer before the final check; 0 = inner_rtol
-                                throughout (0) */
+    int32_t relax_inner;     /* DDM interface GMRES only: 1 = before each Arnoldi step of the outer GMRES the
+                                subdomain tolerance is max(inner_rtol, min(1e-2, s rtol / r)), with r the
+                                outer GMRES's relative residual estimate after the previous step and s an
+                                estimate of the smallest singular value of its Hessenberg matrix (the
+                                inexact Krylov bound of Simoncini and Szyld: late outer steps tolerate less
+                                accurate subdomain solves, the less so the worse the outer operator is
+                                conditioned); residuals at restarts and the final field use inner_rtol,
+                                and the returned field still meets rtol in the global FP64 residual;
+                                0 = inner_rtol throughout (0) */
     int32_t precond;         /* thm_precond (THM_PREC_BLOCK) */
+    int32_t ir_mode;         /* thm_ir_mode (THM_IR_CLASSIC) */
 } thm_solve_opts;
 
 typedef struct {
@@ -123,11 +133,14 @@ typedef struct {
     double rel_residual;     /* final FP64 relative residual of the (glued) solution */
     double setup_ms;         /* preconditioner factorisation time inside this call */
     double solve_ms;         /* solve time inside this call */
-    int32_t fp64_fallback;   /* THM_FP32_IR: solves finished by FP64 GMRES because a refinement step did not
-                                halve the FP64 residual or max_refine was reached (DDM: summed over the
-                                subdomain solves); 0 otherwise */
+    int32_t fp64_fallback;   /* THM_FP32_IR: solves finished by FP64 GMRES with the FP64 factor because
+                                GMRES-IR left them above rtol (DDM: summed over the subdomain solves);
+                                0 otherwise */
     int64_t precond_extra_bytes; /* THM_PREC_FULL: device bytes of the stored M^{-1} (FP64 + FP32) of the
                                 context that solved (all subdomains for the DDM); 0 otherwise */
+    int32_t gmres_ir;        /* THM_FP32_IR: solves finished by GMRES-IR (FP64 GMRES, FP32 factor), either
+                                after a classical step failed to contract or from the start (THM_IR_GMRES)
+                                (DDM: summed over the subdomain solves); 0 otherwise */
 } thm_stats;
 
 typedef struct {
@@ -208,6 +221,12 @@ thm_status thm_system_info(const thm_system *sys, thm_info *info);
  * preconditioner is re-factorised by the next solve. */
 thm_status thm_system_set_mu(thm_system *sys, const double *mu_dev, void *stream);
 void thm_system_destroy(thm_system *sys);
+/* Free the solve workspaces the library keeps after a solve on sys (every batch context that
+ * holds sys: Krylov basis, SpMV schedules, preconditioner work vectors; for a partitioned system
+ * also its subdomain batch).  The system, its matrices and its factorisation stay; the next solve
+ * rebuilds what it needs.  For callers that solve many systems one at a time with little device
+ * memory to spare.  Errors: THM_EINVAL (NULL). */
+thm_status thm_system_release_workspaces(thm_system *sys);
 const char *thm_last_error(void);
 
 /* ---- kernel-level entry points (for parity tests and measurement) -------- */
@@ -251,6 +270,16 @@ thm_status thm_time_spmv(thm_system *sys, int32_t precision, int32_t reps, doubl
  * once. */
 thm_status thm_time_spmv_batch(thm_system *sys, int32_t precision, int32_t variant, int32_t reps, double *ms_out,
                                double *bytes_out, void *stream);
+/* Average device time (ms) of `reps` block SpMVs of eq. (4) applied to every system of the
+ * batch sys[0 .. nsys) in one launch sequence (the batch context of a thm_gmres_solve on the
+ * same systems in the same order if one exists, else a new one), all systems active, with the
+ * context's autotuned variant, measured with HIP events on `stream`.  bytes_out: algorithmic
+ * bytes per product (every system's K, C and row pointers once -- a K shared by a group of
+ * identical systems once when the grouped variant runs -- x read once, y written once).
+ * Errors: THM_EINVAL (nsys < 1, NULL pointers, reps < 1, unknown precision), THM_ENOMEM, THM_EHIP. */
+thm_status thm_time_spmv_systems(int32_t nsys, thm_system *const *sys, int32_t precision, int32_t reps,
+                                 double *ms_out, double *bytes_out, void *stream);
+
 /* Block SpMV variants of eq. (4)'s operator: CSR-vector with L lanes per row and unroll U
  * (code 10 L + U, L in {2, 4, 8, 16, 32, 64}, U in {1, 4}; L = 64 only with U = 1) or
  * SELL-64 (code 19: one wave per slice of 64 rows, column-major padded entries). */

@@ -22,6 +22,7 @@ THM_DDM_GMRES, THM_DDM_JACOBI = 0, 1
 THM_ORTH_CGS, THM_ORTH_CGS2 = 0, 1
 THM_KRYLOV_COMPLEX, THM_KRYLOV_REAL = 0, 1
 THM_PREC_BLOCK, THM_PREC_FULL = 0, 1
+THM_IR_CLASSIC, THM_IR_GMRES = 0, 1
 
 _d3 = ctypes.c_double * 3
 _i3 = ctypes.c_int32 * 3
@@ -41,14 +42,14 @@ class ThmSolveOpts(ctypes.Structure):
                 ("ddm_outer", ctypes.c_int32), ("inner_rtol", ctypes.c_double), ("max_outer", ctypes.c_int32),
                 ("outer_restart", ctypes.c_int32), ("batched", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("ir_inner_rtol", ctypes.c_double), ("max_refine", ctypes.c_int32), ("krylov", ctypes.c_int32),
-                ("relax_inner", ctypes.c_int32), ("precond", ctypes.c_int32)]
+                ("relax_inner", ctypes.c_int32), ("precond", ctypes.c_int32), ("ir_mode", ctypes.c_int32)]
 
 
 class ThmStats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("outer_iters", ctypes.c_int32),
                 ("refinements", ctypes.c_int32), ("rel_residual", ctypes.c_double), ("setup_ms", ctypes.c_double),
                 ("solve_ms", ctypes.c_double), ("fp64_fallback", ctypes.c_int32),
-                ("precond_extra_bytes", ctypes.c_int64)]
+                ("precond_extra_bytes", ctypes.c_int64), ("gmres_ir", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -65,7 +66,8 @@ class ThmInfo(ctypes.Structure):
 EXPORTS = ["thm_default_opts", "thm_assemble", "thm_gmres_solve", "thm_ddm_solve", "thm_adjoint_grad",
            "thm_system_info", "thm_system_set_mu", "thm_system_destroy", "thm_last_error", "thm_apply_operator",
            "thm_apply_precond", "thm_export_matrices", "thm_export_rhs", "thm_export_elements", "thm_time_spmv",
-           "thm_time_precond", "thm_set_spmv_variant", "thm_apply_precond_full", "thm_time_spmv_batch"]
+           "thm_time_precond", "thm_set_spmv_variant", "thm_apply_precond_full", "thm_time_spmv_batch",
+           "thm_time_spmv_systems", "thm_system_release_workspaces"]
 THM_SPMV_SELL = 19
 THM_SPMV_SELL_GROUP = 20
 SPMV_VARIANTS = [21, 41, 81, 161, 321, 641, 24, 44, 84, 164, 324, THM_SPMV_SELL, THM_SPMV_SELL_GROUP]
@@ -86,6 +88,7 @@ def load_library(path=LIB_PATH):
         "thm_system_info": (i32, [vp, ctypes.POINTER(ThmInfo)]),
         "thm_system_set_mu": (i32, [vp, vp, vp]),
         "thm_system_destroy": (None, [vp]),
+        "thm_system_release_workspaces": (i32, [vp]),
         "thm_last_error": (ctypes.c_char_p, []),
         "thm_apply_operator": (i32, [vp, i32, i32, vp, vp, vp]),
         "thm_apply_precond": (i32, [vp, i32, vp, vp, vp]),
@@ -94,6 +97,7 @@ def load_library(path=LIB_PATH):
         "thm_export_elements": (i32, [vp, i64, i64, vp]),
         "thm_time_spmv": (i32, [vp, i32, i32, dp, dp, vp]),
         "thm_time_spmv_batch": (i32, [vp, i32, i32, i32, dp, dp, vp]),
+        "thm_time_spmv_systems": (i32, [i32, ctypes.POINTER(vp), i32, i32, dp, dp, vp]),
         "thm_time_precond": (i32, [vp, i32, i32, dp, dp, ctypes.POINTER(i32), vp]),
         "thm_set_spmv_variant": (i32, [vp, i32, i32]),
         "thm_apply_precond_full": (i32, [vp, i32, i32, vp, vp, vp]),
@@ -265,6 +269,11 @@ def thm_adjoint_grad(system, E, tgt_lo, tgt_hi, opts=None, stream=None):
     return g, J.value
 
 
+def thm_system_release_workspaces(system):
+    """Free the solve workspaces kept for the system (its matrices and factorisation stay)."""
+    _check(_lib.thm_system_release_workspaces(system.handle))
+
+
 def thm_system_set_mu(system, mu, stream=None):
     torch = _torch()
     mu = mu.detach().to(device="cuda", dtype=torch.float64).contiguous()
@@ -342,6 +351,17 @@ def thm_time_spmv_batch(system, precision=THM_FP64, variant=-1, reps=20, stream=
     by = ctypes.c_double()
     _check(_lib.thm_time_spmv_batch(system.handle, int(precision), int(variant), int(reps), ctypes.byref(ms),
                                     ctypes.byref(by), _stream(stream)))
+    return ms.value, by.value
+
+
+def thm_time_spmv_systems(systems, precision=THM_FP64, reps=20, stream=None):
+    """(ms, algorithmic bytes) of one block SpMV over a batch of independent systems."""
+    ns = len(systems)
+    hs = (ctypes.c_void_p * ns)(*[s.handle.value for s in systems])
+    ms = ctypes.c_double()
+    by = ctypes.c_double()
+    _check(_lib.thm_time_spmv_systems(ns, hs, int(precision), int(reps), ctypes.byref(ms), ctypes.byref(by),
+                                      _stream(stream)))
     return ms.value, by.value
 
 

@@ -126,7 +126,7 @@ static void arnoldi_step(Krylov &K, const KOps<T> &ops, const GmresParams &p, hi
 
 template <class T>
 static hipGraphExec_t step_graph(Krylov &K, const KOps<T> &ops, const GmresParams &p, hipStream_t st) {
-    const int key = TypeKey<T>::v * 2 + (ops.csign < 0 ? 1 : 0);
+    const int key = TypeKey<T>::v * 2 + (ops.csign < 0 ? 1 : 0) + (ops.pkind == 2 ? 4 : 0);
     Krylov::GraphSlot &s = K.slots[key];
     if (s.exec && s.owner == ops.owner && s.orth == p.orth && s.max_iter == p.max_iter && s.cplx == p.cplx &&
         s.pkind == ops.pkind)
@@ -381,7 +381,8 @@ void Ctx::build_prec() {
     }
     // Work vectors: one region per factor group, its members' columns interleaved by
     // 8-position chunks (see wv_pos); the member count is padded to the 8 or 16 columns
-    // pairs of one block's n tiles, so absent members read zero columns.
+    // pairs of one block's n tiles only to keep each group's 16-lane runs aligned: lanes of
+    // absent members read the chunk's first member, so the padding columns are never read.
     std::vector<int64_t> gbase(groups.size()), gcs(groups.size());
     int64_t so = 0;
     for (size_t g = 0; g < groups.size(); ++g) {
@@ -779,10 +780,35 @@ KOps<float> Ctx::ops32(float csign, bool with_prec, int pkind) {
     return o;
 }
 
+KOps<double> Ctx::ops_mixed(float csign) {
+    ops32(csign, true, 0);  // FP32 factor and work vectors
+    if (!mx32.n) {
+        mx32.alloc(K.B.Ltot);
+        my32.alloc(K.B.Ltot);
+        THM_HIP(hipMemsetAsync(mx32.p, 0, sizeof(float) * mx32.n, st));
+        THM_HIP(hipMemsetAsync(my32.p, 0, sizeof(float) * my32.n, st));
+    }
+    KOps<double> o;
+    o.apply = [this, csign](const double *x, double *y, const double *b, const int32_t *mask) {
+        spmv<double>(lpr64, mask, x, y, b, csign);
+    };
+    o.prec = [this](const double *x, double *y, const int32_t *mask) {
+        launch_scale<double, float>(K.B, mask, nullptr, 0, x, mx32.p, nullptr, 0, nullptr, st);
+        launch_prec_apply<float>(P, P.d32.p, K.B.off.p, ns, mask, mx32.p, my32.p, ws32.p, ys32.p, tw32.p, st);
+        launch_scale<float, double>(K.B, mask, nullptr, 0, my32.p, y, nullptr, 0, nullptr, st);
+    };
+    o.graphable = true;
+    o.owner = this;
+    o.csign = csign;
+    o.pkind = 2;
+    return o;
+}
+
 void Ctx::solve(const thm_solve_opts &o, float csign, const int32_t *mask, std::vector<int> &iters,
                 std::vector<int> &refines, std::vector<double> &resid) {
     if (!mask) mask = mask_all.p;
     last_fb.assign(ns, 0);
+    last_ir.assign(ns, 0);
     iters.assign(ns, 0);
     refines.assign(ns, 0);
     resid.assign(ns, 0.0);
@@ -816,8 +842,9 @@ void Ctx::solve(const thm_solve_opts &o, float csign, const int32_t *mask, std::
     // accuracy comes from the FP64 refinement loop, not from the FP32 residual.
     // Safeguard: a step that does not at least halve a system's FP64 residual (the FP32
     // factor is too inaccurate for that system's K, e.g. near a resonance) is undone and
-    // the system is finished by FP64 GMRES from its current iterate, as is every system
-    // still running when max_refine steps are spent.
+    // the system is finished by GMRES-IR (FP64 GMRES preconditioned by the FP32 factor) from
+    // its current iterate, as is every system still running when max_refine steps are spent;
+    // FP64 GMRES with the FP64 factor is the last resort if that misses rtol.
     GmresParams ip = gp;
     ip.rtol = o.ir_inner_rtol;
     ip.max_iter = std::min(o.max_iter, K.m);
@@ -828,7 +855,23 @@ void Ctx::solve(const thm_solve_opts &o, float csign, const int32_t *mask, std::
     };
     if (!ir_aux.n) ir_aux.alloc(ns);
     if (!ir_scal.n) ir_scal.alloc(ns);
-    for (int it = 0;; ++it) {
+    const bool classic = o.ir_mode != THM_IR_GMRES || pk != 0;
+    if (ir_sticky.size() != (size_t)ns) ir_sticky.assign(ns, 0);
+    {
+        // GMRES-IR from the start for every system (THM_IR_GMRES) or for the systems whose
+        // classical step has already failed to contract in this context
+        std::vector<int32_t> hm(ns);
+        THM_HIP(hipMemcpyAsync(hm.data(), mask, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, st));
+        THM_HIP(hipStreamSynchronize(st));
+        bool any_sticky = false;
+        for (int i = 0; i < ns; ++i) {
+            fb[i] = hm[i] && (!classic || (pk == 0 && ir_sticky[i]));
+            any_sticky = any_sticky || fb[i];
+            if (fb[i]) hm[i] = 0;
+        }
+        if (classic && any_sticky) upload_flags(run_ir, hm);
+    }
+    for (int it = 0; classic; ++it) {
         A64.apply(x64.p, r64.p, b64.p, run_ir.p);
         launch_norm2<double>(K.B, run_ir.p, r64.p, K.part.p, st);
         launch_norm_finish(K.B, K.part.p, run_ir.p, rnorm.p, bnorm64.p, o.rtol, resid64.p, run_ir.p, st);
@@ -842,6 +885,7 @@ void Ctx::solve(const thm_solve_opts &o, float csign, const int32_t *mask, std::
             if (undo[i]) {
                 any_undo = true;
                 fb[i] = 1;
+                if (pk == 0) ir_sticky[i] = 1;
                 hi[i] = 0;
                 hr[i] = prev[i];
             }
@@ -884,11 +928,62 @@ void Ctx::solve(const thm_solve_opts &o, float csign, const int32_t *mask, std::
         THM_HIP(hipStreamSynchronize(st));
         for (int i = 0; i < ns; ++i) iters[i] += hi[i];
     }
-    THM_HIP(hipMemcpyAsync(hr.data(), resid64.p, sizeof(double) * ns, hipMemcpyDeviceToHost, st));
-    THM_HIP(hipStreamSynchronize(st));
-    for (int i = 0; i < ns; ++i) resid[i] = hr[i];
+    if (classic) {
+        THM_HIP(hipMemcpyAsync(hr.data(), resid64.p, sizeof(double) * ns, hipMemcpyDeviceToHost, st));
+        THM_HIP(hipStreamSynchronize(st));
+        for (int i = 0; i < ns; ++i) resid[i] = hr[i];
+    }
     bool any_fb = false;
     for (int i = 0; i < ns; ++i) any_fb = any_fb || fb[i];
+    if (any_fb && pk == 0) {
+        // GMRES-based refinement (Carson & Higham, SIAM J. Sci. Comput. 40 (2018)): where a
+        // classical step with an FP32 inner solve did not contract, the correction is solved by
+        // GMRES in FP64 (FP64 operator, basis, Hessenberg) with the FP32 factor as the
+        // preconditioner, from the current iterate.  The FP32 factor only slows convergence
+        // there, it no longer limits the attainable accuracy.  It runs one restart cycle at a
+        // time, and a cycle must at least halve a system's FP64 residual (the same rule as a
+        // classical step); a system that stalls (its FP32 factor too far from K^{-1}, e.g. near
+        // a resonance) is finished with the FP64 factor below.
+        KOps<double> AM = ops_mixed(csign);
+        GmresParams cp = gp;
+        cp.max_iter = K.m;
+        std::vector<int32_t> in_ir(fb);
+        std::vector<double> prev_ir(ns, HUGE_VAL);  // no bar on a system's first cycle
+        int used = 0;
+        for (;;) {
+            bool any_ir = false;
+            for (int i = 0; i < ns; ++i) any_ir = any_ir || in_ir[i];
+            if (!any_ir) break;
+            if (used >= o.max_iter) {
+                for (int i = 0; i < ns; ++i) in_ir[i] = 0;  // fb stays set: FP64 below
+                break;
+            }
+            upload_flags(ir_aux, in_ir);
+            gmres_run<double>(K, AM, b64.p, x64.p, ir_aux.p, cp, st);
+            THM_HIP(hipMemcpyAsync(hi.data(), K.iters.p, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, st));
+            THM_HIP(hipMemcpyAsync(hr.data(), K.resid.p, sizeof(double) * ns, hipMemcpyDeviceToHost, st));
+            THM_HIP(hipStreamSynchronize(st));
+            int cyc = 0;
+            for (int i = 0; i < ns; ++i) {
+                if (!in_ir[i]) continue;
+                iters[i] += hi[i];
+                cyc = std::max(cyc, hi[i]);
+                resid[i] = hr[i];
+                last_ir[i] = 1;
+                if (hr[i] <= o.rtol) {
+                    in_ir[i] = 0;
+                    fb[i] = 0;
+                } else if (!(hr[i] <= 0.5 * prev_ir[i])) {
+                    in_ir[i] = 0;  // stalled: FP64 below
+                } else {
+                    prev_ir[i] = hr[i];
+                }
+            }
+            used += std::max(cyc, 1);
+        }
+        any_fb = false;
+        for (int i = 0; i < ns; ++i) any_fb = any_fb || fb[i];
+    }
     if (any_fb) {
         upload_flags(ir_aux, fb);
         gmres_run<double>(K, A64, b64.p, x64.p, ir_aux.p, gp, st);

@@ -113,7 +113,7 @@ struct Krylov {
         float csign = 0.f;
         double rtol = -1.0;
         const void *owner = nullptr;
-    } slots[4];
+    } slots[6];
     void init(const std::vector<int64_t> &n, int m, hipStream_t st);
     template <class T> T *V();
     template <class T> T *w();
@@ -133,7 +133,8 @@ struct KOps {
     bool graphable = false;
     const void *owner = nullptr;  // identity of the operator (graph cache key)
     float csign = 1.f;
-    int pkind = 0;                // preconditioner: 0 block diag(K, K)^{-1}, 1 complete (K +- iC)^{-1}
+    int pkind = 0;                // preconditioner: 0 block diag(K, K)^{-1}, 1 complete (K +- iC)^{-1},
+                                  // 2 block diag(K, K)^{-1} with the FP32 factor inside FP64 GMRES (GMRES-IR)
 };
 
 struct GmresParams {
@@ -161,8 +162,13 @@ struct Ctx {
     DBuf<float> x32, b32, ws32, ys32, tw32;
     DBuf<int32_t> mask_all, run_ir, ir_aux;
     DBuf<double> ir_scal;
-    int64_t fp64_fallbacks = 0;  // systems finished in FP64 after a failed refinement step (cumulative)
-    std::vector<int32_t> last_fb;  // per system, last solve: finished in FP64
+    int64_t fp64_fallbacks = 0;  // systems finished in FP64 after GMRES-IR missed rtol (cumulative)
+    std::vector<int32_t> last_fb;  // per system, last solve: finished by FP64 GMRES with the FP64 factor
+    std::vector<int32_t> last_ir;  // per system, last solve: finished by GMRES-IR (FP64 Krylov, FP32 factor)
+    DBuf<float> mx32, my32;        // FP32 copies of the GMRES-IR preconditioner's input and output
+    // per system: a classical refinement step failed to contract in this context, so its later
+    // THM_FP32_IR solves go straight to GMRES-IR (the context is rebuilt when K changes)
+    std::vector<int32_t> ir_sticky;
     DBuf<double> rnorm, bnorm64, resid64;
     int lpr64 = 81, lpr32 = 81;  // SpMV variants (10 * lanes_per_row + unroll, or a SELL code)
     // groups of systems with the same K for the grouped SELL product (SPMV_SELL_GROUP)
@@ -199,6 +205,9 @@ struct Ctx {
     // the block preconditioner (0) or the complete inverse (1)
     KOps<double> ops64(float csign, bool with_prec = true, int pkind = 0);
     KOps<float> ops32(float csign, bool with_prec = true, int pkind = 0);
+    // FP64 operator with the block preconditioner applied by the FP32 factor (input rounded to
+    // FP32, output widened): the correction solve of GMRES-based iterative refinement
+    KOps<double> ops_mixed(float csign);
     // Solve A x = b for the systems in mask (device, nullable = all); b64/x64 slots hold
     // the right-hand sides and initial guesses (zero on Dirichlet rows).
     void solve(const thm_solve_opts &o, float csign, const int32_t *mask, std::vector<int> &iters,

@@ -1,13 +1,23 @@
-"""GPU parity on the benchmark configurations (full size where the oracle is fast enough,
-otherwise the same recipe at reduced size) against the oracle."""
+"""GPU parity on the benchmark configurations against the oracle: at full size where the
+oracle's LU is fast enough (the 256^2 four-by-four DDM, the 256-problem batch, the adjoint
+case), otherwise at 16^3 and 8^3 for the 3D recipe.
+
+Protocol: FP64 solves run to rtol 1e-13 and match the oracle to 1e-10 (relative l2 of the
+full complex DoF vector); FP32 inner solves with FP64 refinement run to 1e-11 and match to
+1e-8.  Runs stopped at the benchmark's 1e-8 are checked by the oracle's own residual of the
+downloaded field."""
+import os
+
 import numpy as np
 import pytest
 
 import workloads
 from oracle import adjoint, system
-from tests._gpu_helpers import problem, rel
+from tests._gpu_helpers import (ddm_fp64, ddm_mixed, oracle_residuals, oracle_solutions, problem, rel)
 
 pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 @pytest.fixture(scope="module")
@@ -20,7 +30,12 @@ def thm():
 
 def test_c5_adjoint_full_size(thm):
     """128^2 quads, p = 1, w = 30, mu from the Gaussian random field: forward solve and the
-    adjoint gradient (16,384 parameters) against the oracle's LU solve and exact gradient."""
+    adjoint gradient (16,384 parameters) against the oracle's LU solve and exact gradient, and
+    central differences of J (GPU solves) on all 32 seeded cells.  The differences use the
+    five-point central formula (8 (J(+h) - J(-h)) - (J(+2h) - J(-2h))) / 12h, h = 1e-5 mu_c:
+    the three-point formula's h^2 truncation term alone reaches 1e-6 of the metric on cells
+    whose derivative is near the metric's floor (measured 1.04e-6 on cell 11004)."""
+    import torch
     d = workloads.c5()
     print("case c5 full", flush=True)
     S = thm.thm_assemble(d)
@@ -34,24 +49,26 @@ def test_c5_adjoint_full_size(thm):
     MT = adjoint.target_mass(so, lo, hi)
     go, _ = adjoint.gradient(so, Eo, MT)
     assert abs(J - adjoint.objective(so, Eo, MT)) <= 1e-9 * abs(J)
-    assert rel(g.cpu().numpy(), go) <= 1e-7
-    # central differences of J with GPU solves on a few of the seeded cells
-    import torch
-    cells = workloads.fd_cells(so.mesh.n_cells)[:4]
+    gh = g.cpu().numpy()
+    assert rel(gh, go) <= 1e-7
+    cells = workloads.fd_cells(so.mesh.n_cells)
+    assert len(cells) == 32
     mu0 = np.asarray(d["mu"], dtype=np.float64)
+    worst = 0.0
     for c in cells:
         h = 1e-5 * mu0[c]
-        Js = []
-        for sgn in (1, -1):
+        Js = {}
+        for k in (2, 1, -1, -2):
             mu = mu0.copy()
-            mu[c] += sgn * h
+            mu[c] += k * h
             thm.thm_system_set_mu(S, torch.from_numpy(mu))
             (Ec,), _ = thm.thm_gmres_solve([S], opts)
-            _, Jc = thm.thm_adjoint_grad(S, Ec, lo, hi, opts)
-            Js.append(Jc)
-        fd = (Js[0] - Js[1]) / (2 * h)
-        gc = g.cpu().numpy()[c]
-        assert abs(gc - fd) <= 1e-6 * max(abs(fd), 1e-3 * np.abs(go).max()), (c, gc, fd)
+            _, Js[k] = thm.thm_adjoint_grad(S, Ec, lo, hi, opts)
+        fd = (8.0 * (Js[1] - Js[-1]) - (Js[2] - Js[-2])) / (12.0 * h)
+        err = abs(gh[c] - fd) / max(abs(fd), 1e-3 * np.abs(go).max())
+        worst = max(worst, err)
+        assert err <= 1e-6, (c, gh[c], fd)
+    print(f"c5: worst FD mismatch over 32 cells {worst:.2e}", flush=True)
 
 
 def test_c4_uneven_batch_reduced(thm):
@@ -69,34 +86,100 @@ def test_c4_uneven_batch_reduced(thm):
         assert rel(E.cpu().numpy(), Eo) <= 1e-8
 
 
-def test_c3_ddm_reduced(thm):
-    """3D recipe (mu ~ U[1,2] per cell, seed 3, w = 20, 2x2x2 subdomains) on 8^3 hexes."""
+def test_c3_ddm_8(thm):
+    """3D recipe (mu ~ U[1,2] per cell, seed 3, w = 20, 2x2x2 subdomains) on 8^3 hexes
+    against the oracle's global LU."""
     d = workloads.c3(m=8)
-    print("case c3 reduced", flush=True)
+    print("case c3 8^3", flush=True)
     S = thm.thm_assemble(d)
     Eg = system.solve_lu(system.assemble(problem(d)))
-    E, st = thm.thm_ddm_solve(S, thm.default_opts(rtol=1e-11, inner_rtol=1e-12, restart=80))
-    assert st["rel_residual"] <= 1e-11
-    assert rel(E.cpu().numpy(), Eg) <= 1e-9
-    E, st = thm.thm_ddm_solve(S, thm.default_opts(rtol=1e-10, inner_rtol=1e-11, restart=80,
-                                                  precision=thm.THM_FP32_IR))
-    assert rel(E.cpu().numpy(), Eg) <= 1e-8
+    E, st = ddm_fp64(thm, S, restart=80)
+    print("c3 8^3 fp64:", st, rel(E, Eg), flush=True)
+    assert st["rel_residual"] <= 1e-12
+    assert rel(E, Eg) <= 1e-10
+    E, st = ddm_mixed(thm, S, restart=80)
+    print("c3 8^3 fp32+refinement:", st, rel(E, Eg), flush=True)
+    assert rel(E, Eg) <= 1e-8
 
 
-def test_c2_full_size_sampled(thm):
-    """The benchmark configuration at full size (1.18M DoFs): the glued DDM field's global
-    residual, recomputed on the CPU from the oracle's own assembled matrices, is below the
-    solver tolerance; sampled DoFs on Gamma^inc equal the oracle's Dirichlet values."""
+def test_c3_ddm_16(thm):
+    """The 3D recipe on 16^3 hexes (104,544 DoFs, 2x2x2 subdomains of 8^3) against the oracle's
+    solution stored by tests/golden/make_c3_reference.py (the oracle's global sparse LU with
+    refinement, residual checked <= 1e-13).  FP64 with the complete inverse of the subdomain
+    systems (fast; the field does not depend on the preconditioner) and FP32 + refinement with
+    the block preconditioner of eq. (11)."""
+    Eg = np.load(os.path.join(GOLDEN, "c3_m16_oracle_E.npy"))
+    d = workloads.c3(m=16)
+    print("case c3 16^3", flush=True)
+    S = thm.thm_assemble(d)
+    assert S.n == Eg.shape[0]
+    E, st = ddm_fp64(thm, S, restart=80, precond=thm.THM_PREC_FULL)
+    print("c3 16^3 fp64 (complete inverse):", st, rel(E, Eg), flush=True)
+    assert st["rel_residual"] <= 1e-12
+    assert rel(E, Eg) <= 1e-10
+    E, st = ddm_mixed(thm, S, restart=80)
+    print("c3 16^3 fp32+refinement (block):", st, rel(E, Eg), flush=True)
+    assert st["rel_residual"] <= 1e-10
+    assert rel(E, Eg) <= 1e-8
+
+
+def test_c3_subdomain_factor_backward_error(thm):
+    """The exact K^{-1} at the shape of one 32^3-recipe subdomain (16^3 hexes, degree 1:
+    17 layers of 4,866 skeleton DoFs, cyclic reduction down to one dense last block), with the
+    recipe's random mu: normwise backward error of K z = x in FP64 and FP32, against the
+    oracle's assembled K.  The explicit inverses of 4,866-wide indefinite pivot blocks grow
+    rounding by about 5e5 here (measured 5.9e-11 in FP64, 2.4e-3 in FP32, against 5e-13 on the
+    small 3D shapes): the bars leave a factor of 10 over that and still fail on a missing,
+    misplaced or wrongly signed tile (an O(1) error).  This FP32 backward error is why 3D
+    mixed precision refines with GMRES-IR rather than with FP32 inner solves."""
+    import torch
+    from tests._gpu_helpers import dirichletized
+    d = dict(workloads.c3(m=16), subdomains=(1, 1, 1))
+    print("case cyclic reduction 16^3 p1", flush=True)
+    S = thm.thm_assemble(d)
+    assert S.info["n_layers"] == 17
+    so = system.assemble(problem(d))
+    K = dirichletized(so)[0].real
+    rng = np.random.default_rng(61)
+    x = rng.standard_normal(S.n) + 1j * rng.standard_normal(S.n)
+    xt = torch.from_numpy(x).cuda()
+    knorm = abs(K).sum(axis=1).max()
+
+    def eta(z):
+        return np.linalg.norm(K @ z - x, np.inf) / (knorm * np.linalg.norm(z, np.inf) + np.linalg.norm(x, np.inf))
+
+    e64 = eta(thm.thm_apply_precond(S, xt).cpu().numpy())
+    e32 = eta(thm.thm_apply_precond(S, xt, precision=thm.THM_FP32_IR).cpu().numpy())
+    print(f"16^3 factor backward error: fp64 {e64:.2e} fp32 {e32:.2e}", flush=True)
+    assert e64 <= 1e-9
+    assert e32 <= 3e-2
+
+
+def test_c2_full_size(thm):
+    """The benchmark configuration at full size (256^2 quads, degree 2, 1,181,184 DoFs, 4x4
+    subdomains) against the oracle's global LU: the timed form (FP32 + refinement, relaxed
+    subdomain tolerance, 1e-8) has an oracle-computed residual <= 1e-8 that agrees with the
+    library's own; FP64 to 1e-13 matches to 1e-10 and FP32 + refinement to 1e-11 matches to
+    1e-8."""
     d = workloads.c2()
     print("case c2 full", flush=True)
     S = thm.thm_assemble(d)
-    E, st = thm.thm_ddm_solve(S, thm.default_opts(rtol=1e-8, inner_rtol=1e-10, restart=64,
-                                                  precision=thm.THM_FP32_IR))
-    assert st["status"] == 0
     so = system.assemble(problem(d))
+    Eo = system.solve_lu(so)
+    E, st = thm.thm_ddm_solve(S, thm.default_opts(rtol=1e-8, inner_rtol=1e-10, restart=64, relax_inner=1,
+                                                  precision=thm.THM_FP32_IR))
     Eh = E.cpu().numpy()
-    assert system.relative_residual(so, Eh) <= 1.5e-8
+    r = system.relative_residual(so, Eh)
+    print(f"c2 timed form: {st}; oracle residual {r:.3e}; error vs LU {rel(Eh, Eo):.2e}", flush=True)
+    assert st["status"] == 0 and r <= 1e-8
+    assert abs(r - st["rel_residual"]) <= 1e-3 * r
     assert rel(Eh[so.D], so.gD) <= 1e-13
+    E, st = ddm_fp64(thm, S, restart=64)
+    print("c2 fp64:", st, rel(E, Eo), flush=True)
+    assert rel(E, Eo) <= 1e-10
+    E, st = ddm_mixed(thm, S, restart=64)
+    print("c2 fp32+refinement:", st, rel(E, Eo), flush=True)
+    assert rel(E, Eo) <= 1e-8
 
 
 def test_refinement_fallback_is_fp64_accurate(thm):
@@ -113,15 +196,60 @@ def test_refinement_fallback_is_fp64_accurate(thm):
     assert rel(E.cpu().numpy(), Eo) <= 1e-10
 
 
-def test_c4_half_size_batch_reaches_tolerance_in_fp32_refinement(thm):
-    """All 256 problems of the uneven batch (meshes halved) reach 1e-8 in the FP32 +
-    refinement form; problems whose FP32 factor is too inaccurate (high w, near-resonant
-    K) are detected by the refinement safeguard and finished in FP64."""
+def test_c4_half_size_batch_every_member(thm):
+    """All 256 problems of the uneven batch with meshes halved, one batched solve, compared
+    member by member with the oracle's LU: FP64 to 1e-10, FP32 + refinement to 1e-8; the
+    benchmark's form (FP32 + refinement to 1e-8) reaches 1e-8 in every member by the
+    oracle's residual."""
     specs = workloads.c4(256, scale=2)
-    print("case c4 half size fp32", flush=True)
+    print("case c4 half size", flush=True)
+    refs = oracle_solutions(specs)
     systems = [thm.thm_assemble(d) for d in specs]
+    Es, sts = thm.thm_gmres_solve(systems, thm.default_opts(rtol=1e-13, restart=64, max_iter=20000))
+    errs = [rel(E.cpu().numpy(), Eo) for E, Eo in zip(Es, refs)]
+    print(f"c4 half fp64: worst error {max(errs):.2e}", flush=True)
+    assert max(errs) <= 1e-10
+    Es, sts = thm.thm_gmres_solve(systems, thm.default_opts(rtol=1e-11, restart=64, max_iter=20000,
+                                                            precision=thm.THM_FP32_IR))
+    errs = [rel(E.cpu().numpy(), Eo) for E, Eo in zip(Es, refs)]
+    print(f"c4 half fp32+refinement: worst error {max(errs):.2e}, fp64 fallbacks "
+          f"{sum(s['fp64_fallback'] for s in sts)}", flush=True)
+    assert max(errs) <= 1e-8
     Es, sts = thm.thm_gmres_solve(systems, thm.default_opts(rtol=1e-8, restart=64, precision=thm.THM_FP32_IR),
                                   allow_not_converged=True)
-    bad = [(i, s["rel_residual"]) for i, s in enumerate(sts) if not (s["status"] == 0 and s["rel_residual"] <= 1e-8)]
-    print("fp64 fallbacks:", sum(s["fp64_fallback"] for s in sts), flush=True)
+    res = oracle_residuals(specs, [E.cpu().numpy() for E in Es])
+    bad = [(i, r, s["rel_residual"]) for i, (r, s) in enumerate(zip(res, sts)) if not r <= 1e-8]
     assert not bad, bad[:5]
+
+
+def test_c4_full_size(thm):
+    """The 256-problem uneven batch at full size (about 18.4M DoFs), one batched solve: 32
+    seeded members compared with the oracle's LU (FP64 to 1e-10, FP32 + refinement to 1e-8),
+    and every member of the benchmark's form (FP32 + refinement to 1e-8) at an
+    oracle-computed residual <= 1e-8."""
+    specs = workloads.c4(256)
+    pick = workloads.c4_sample()
+    print("case c4 full size", flush=True)
+    import gc
+    import torch
+    gc.collect()
+    torch.cuda.empty_cache()
+    refs = oracle_solutions([specs[i] for i in pick])
+    systems = [thm.thm_assemble(d) for d in specs]
+    print("c4 full: DoFs", sum(s.n for s in systems), flush=True)
+    # restart 32: the factors of the whole batch take 243 GB of the 288 GB
+    Es, sts = thm.thm_gmres_solve(systems, thm.default_opts(rtol=1e-13, restart=32, max_iter=40000))
+    errs = [rel(Es[i].cpu().numpy(), Eo) for i, Eo in zip(pick, refs)]
+    print(f"c4 full fp64: worst error {max(errs):.2e}", flush=True)
+    assert max(errs) <= 1e-10
+    Es, sts = thm.thm_gmres_solve(systems, thm.default_opts(rtol=1e-11, restart=32, max_iter=40000,
+                                                            precision=thm.THM_FP32_IR))
+    errs = [rel(Es[i].cpu().numpy(), Eo) for i, Eo in zip(pick, refs)]
+    print(f"c4 full fp32+refinement: worst error {max(errs):.2e}", flush=True)
+    assert max(errs) <= 1e-8
+    Es, sts = thm.thm_gmres_solve(systems, thm.default_opts(rtol=1e-8, restart=32, max_iter=40000,
+                                                            precision=thm.THM_FP32_IR), allow_not_converged=True)
+    res = oracle_residuals(specs, [E.cpu().numpy() for E in Es])
+    print(f"c4 full timed form: worst oracle residual {max(res):.2e}, fp64 fallbacks "
+          f"{sum(s['fp64_fallback'] for s in sts)}", flush=True)
+    assert max(res) <= 1e-8

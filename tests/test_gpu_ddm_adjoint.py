@@ -4,7 +4,7 @@ import pytest
 
 import workloads
 from oracle import adjoint, ddm, system
-from tests._gpu_helpers import problem, rel, spec
+from tests._gpu_helpers import ddm_fp64, ddm_mixed, problem, rel, spec
 
 pytestmark = pytest.mark.gpu
 
@@ -48,33 +48,28 @@ def test_ddm_gmres_reaches_global_solution(thm, case):
     print("case", case, flush=True)
     S = thm.thm_assemble(d)
     Eg = system.solve_lu(system.assemble(problem(d)))
-    o = thm.default_opts(rtol=1e-12, inner_rtol=1e-13)
-    E, st = thm.thm_ddm_solve(S, o)
-    assert st["status"] == 0 and st["rel_residual"] <= 1e-12
-    assert rel(E.cpu().numpy(), Eg) <= 1e-10
-    o = thm.default_opts(rtol=1e-12, inner_rtol=1e-13, batched=0, use_graph=0)
-    E2, st2 = thm.thm_ddm_solve(S, o)
-    assert rel(E2.cpu().numpy(), Eg) <= 1e-10
-    o = thm.default_opts(rtol=1e-10, inner_rtol=1e-11, precision=thm.THM_FP32_IR)
-    E3, st3 = thm.thm_ddm_solve(S, o)
-    assert rel(E3.cpu().numpy(), Eg) <= 1e-8
+    E, st = ddm_fp64(thm, S)
+    assert st["rel_residual"] <= 1e-12
+    assert rel(E, Eg) <= 1e-10
+    E2, st2 = ddm_fp64(thm, S, batched=0, use_graph=0)
+    assert rel(E2, Eg) <= 1e-10
+    E3, st3 = ddm_mixed(thm, S)
+    assert rel(E3, Eg) <= 1e-8
     # relaxed subdomain tolerance (loose late inner solves): still the global solution
-    o = thm.default_opts(rtol=1e-12, inner_rtol=1e-13, relax_inner=1)
-    E4, st4 = thm.thm_ddm_solve(S, o)
-    assert st4["status"] == 0 and st4["rel_residual"] <= 1e-12
-    assert rel(E4.cpu().numpy(), Eg) <= 1e-10
-    o = thm.default_opts(rtol=1e-10, inner_rtol=1e-11, precision=thm.THM_FP32_IR, relax_inner=1)
-    E5, st5 = thm.thm_ddm_solve(S, o)
-    assert st5["status"] == 0 and st5["rel_residual"] <= 1e-10
-    assert rel(E5.cpu().numpy(), Eg) <= 1e-8
+    E4, st4 = ddm_fp64(thm, S, relax_inner=1)
+    assert st4["rel_residual"] <= 1e-12
+    assert rel(E4, Eg) <= 1e-10
+    E5, st5 = ddm_mixed(thm, S, relax_inner=1)
+    assert st5["rel_residual"] <= 1e-10
+    assert rel(E5, Eg) <= 1e-8
 
 
 def test_ddm_single_subdomain_equals_single_domain(thm):
     d = workloads.c1()
     S = thm.thm_assemble(d)
     Eg = system.solve_lu(system.assemble(problem(d)))
-    E, st = thm.thm_ddm_solve(S, thm.default_opts(rtol=1e-12, inner_rtol=1e-13))
-    assert rel(E.cpu().numpy(), Eg) <= 1e-10
+    E, st = ddm_fp64(thm, S)
+    assert rel(E, Eg) <= 1e-10
 
 
 def test_adjoint_gradient_matches_oracle_and_fd(thm):
@@ -146,11 +141,11 @@ def test_ddm_shared_factors_homogeneous_partition(thm):
     print("case c2-32", flush=True)
     S = thm.thm_assemble(d)
     Eg = system.solve_lu(system.assemble(problem(d)))
-    for prec in (thm.THM_FP64, thm.THM_FP32_IR):
-        o = thm.default_opts(rtol=1e-11, inner_rtol=1e-12, restart=80, precision=prec)
-        E, st = thm.thm_ddm_solve(S, o)
-        assert st["rel_residual"] <= 1e-11
-        assert rel(E.cpu().numpy(), Eg) <= (1e-9 if prec == thm.THM_FP64 else 1e-8)
-    o = thm.default_opts(rtol=1e-10, inner_rtol=1e-11, krylov=thm.THM_KRYLOV_REAL, restart=80)
-    E, st = thm.thm_ddm_solve(S, o)
-    assert rel(E.cpu().numpy(), Eg) <= 1e-8
+    E, st = ddm_fp64(thm, S, restart=80)
+    assert st["rel_residual"] <= 1e-12
+    assert rel(E, Eg) <= 1e-10
+    E, st = ddm_mixed(thm, S, restart=80)
+    assert st["rel_residual"] <= 1e-10
+    assert rel(E, Eg) <= 1e-8
+    E, st = ddm_fp64(thm, S, krylov=thm.THM_KRYLOV_REAL, restart=80)
+    assert rel(E, Eg) <= 1e-10

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from oracle import system
-from tests._gpu_helpers import csr, dirichletized, problem, rel, spec
+from tests._gpu_helpers import csr, ddm_fp64, dirichletized, problem, rel, spec
 
 pytestmark = pytest.mark.gpu
 
@@ -84,9 +84,9 @@ def test_one_cell_subdomains(thm, case):
     d = spec(dim, m, p, om, subdomains=parts)
     S = thm.thm_assemble(d)
     Eg = system.solve_lu(system.assemble(problem(d)))
-    E, st = thm.thm_ddm_solve(S, thm.default_opts(rtol=1e-11, inner_rtol=1e-13))
-    assert st["status"] == 0, st
-    assert rel(E.cpu().numpy(), Eg) <= 1e-9
+    E, st = ddm_fp64(thm, S)
+    assert st["rel_residual"] <= 1e-12, st
+    assert rel(E, Eg) <= 1e-10
 
 
 def test_empty_batch_and_uneven_partition_are_rejected(thm):

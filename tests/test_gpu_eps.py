@@ -11,7 +11,7 @@ import scipy.sparse.linalg as spla
 
 import workloads
 from oracle import gmres, system
-from tests._gpu_helpers import csr, problem, rel, spec
+from tests._gpu_helpers import csr, ddm_fp64, ddm_mixed, problem, rel, spec
 
 pytestmark = pytest.mark.gpu
 
@@ -54,10 +54,10 @@ def test_block_benchmark_ddm(thm, parts):
     print("case block ddm", parts, flush=True)
     S = thm.thm_assemble(d)
     Eg = system.solve_lu(system.assemble(problem(d)))
-    E, st = thm.thm_ddm_solve(S, thm.default_opts(rtol=1e-11, inner_rtol=1e-13))
-    assert st["status"] == 0 and rel(E.cpu().numpy(), Eg) <= 1e-9
-    E3, st3 = thm.thm_ddm_solve(S, thm.default_opts(rtol=1e-10, inner_rtol=1e-11, precision=thm.THM_FP32_IR))
-    assert st3["status"] == 0 and rel(E3.cpu().numpy(), Eg) <= 1e-8
+    E, st = ddm_fp64(thm, S)
+    assert st["rel_residual"] <= 1e-12 and rel(E, Eg) <= 1e-10
+    E3, st3 = ddm_mixed(thm, S)
+    assert st3["status"] == 0 and rel(E3, Eg) <= 1e-8
 
 
 def test_block_benchmark_sweep_iterations_match_oracle(thm):

@@ -29,7 +29,7 @@ def thm():
 def _solve_pinned(thm, S, variant, o):
     for p in (thm.THM_FP64, thm.THM_FP32_IR):
         thm.thm_set_spmv_variant(S, p, variant)
-    E, st = thm.thm_ddm_solve(S, o)
+    E, st = thm.thm_ddm_solve(S, o, allow_not_converged=True)
     return E.cpu().numpy(), st
 
 
@@ -38,20 +38,20 @@ def test_grouped_product_is_bitwise_sell_on_homogeneous_partition(thm, fp32):
     d = dict(workloads.c2(32))
     print("case c2-32 grouped spmv", "fp32ir" if fp32 else "fp64", flush=True)
     S = thm.thm_assemble(d)
-    o = thm.default_opts(rtol=1e-11, inner_rtol=1e-12, restart=80,
-                         precision=thm.THM_FP32_IR if fp32 else thm.THM_FP64)
-    thm.thm_ddm_solve(S, o)  # builds the batched subdomain context
+    from tests._gpu_helpers import FP64_TIGHT, MIXED_TIGHT
+    o = thm.default_opts(restart=80, **(dict(MIXED_TIGHT, precision=thm.THM_FP32_IR) if fp32 else FP64_TIGHT))
+    thm.thm_ddm_solve(S, o, allow_not_converged=True)  # builds the batched subdomain context
     groups = S.fresh_info()["ddm_spmv_groups"]
     # the 4 subdomains on x = 0 carry Dirichlet rows, the other 12 share one K
     assert groups == 2
     E19, st19 = _solve_pinned(thm, S, thm.THM_SPMV_SELL, o)
     E20, st20 = _solve_pinned(thm, S, thm.THM_SPMV_SELL_GROUP, o)
     assert S.fresh_info()["ddm_spmv_variant"] == thm.THM_SPMV_SELL_GROUP
-    assert st19["status"] == 0 and st20["status"] == 0
+    assert st19["rel_residual"] <= (1e-10 if fp32 else 1e-12) and st20["rel_residual"] == st19["rel_residual"]
     assert st19["iters"] == st20["iters"] and st19["outer_iters"] == st20["outer_iters"]
     assert np.array_equal(E19, E20)
     Eg = system.solve_lu(system.assemble(problem(d)))
-    assert rel(E20, Eg) <= (1e-8 if fp32 else 1e-9)
+    assert rel(E20, Eg) <= (1e-8 if fp32 else 1e-10)
 
 
 def test_grouped_product_with_distinct_subdomains(thm):
@@ -60,13 +60,14 @@ def test_grouped_product_with_distinct_subdomains(thm):
              inc_dir=(np.cos(0.3), np.sin(0.3), 0.0), inc_pol=(-np.sin(0.3), np.cos(0.3), 0.0))
     print("case random-mu 3x2 grouped spmv", flush=True)
     S = thm.thm_assemble(d)
-    o = thm.default_opts(rtol=1e-11, inner_rtol=1e-13)
-    thm.thm_ddm_solve(S, o)
+    from tests._gpu_helpers import FP64_TIGHT
+    o = thm.default_opts(**FP64_TIGHT)
+    thm.thm_ddm_solve(S, o, allow_not_converged=True)
     assert S.fresh_info()["ddm_spmv_groups"] == 6
     E, st = _solve_pinned(thm, S, thm.THM_SPMV_SELL_GROUP, o)
-    assert st["status"] == 0
+    assert st["rel_residual"] <= 1e-12
     Eg = system.solve_lu(system.assemble(problem(d)))
-    assert rel(E, Eg) <= 1e-9
+    assert rel(E, Eg) <= 1e-10
 
 
 def test_batched_spmv_timing_counts_each_distinct_k_once(thm):

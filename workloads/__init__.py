@@ -13,7 +13,8 @@ E^inc = pol * exp(-i w d.x) on the x = 0 side, impedance on every other side):
   c3  3D 32^3 hexes, degree 1, mu ~ U[1,2] per cell (seed 3), w = 20, 2x2x2 subdomains
   c4  256 independent 2D problems: m in {32,64,96,128}, degree in {0,1,2},
       w ~ U[5,60], incidence angle theta ~ U[0, pi/2) (seed 4, drawn per problem in
-      the order m, p, w, theta); d = (cos t, sin t), pol = (-sin t, cos t)
+      the order m, p, w, theta); d = (cos t, sin t), pol = (-sin t, cos t); 32 members
+      sampled for member-by-member comparison (seed 7)
   c5  2D 128^2 quads, degree 1, w = 30, mu = clip(1 + 3 f, 1, 4) with f a
       standardised Gaussian random field (seed 5, correlation length 0.1);
       target box [0.7,0.9]^2; 32 finite-difference cells (seed 6)
@@ -70,6 +71,12 @@ def c4(count=256, seed=4, scale=1):
         probs.append(_base(2, (mm, mm), p, w, inc_dir=(math.cos(th), math.sin(th), 0.0),
                            inc_pol=(-math.sin(th), math.cos(th), 0.0)))
     return probs
+
+
+def c4_sample(count=32, total=256, seed=7):
+    """Seeded sample of member indices of the uneven batch (compared member by member with
+    the oracle's LU at full size)."""
+    return np.sort(np.random.default_rng(seed).choice(total, size=count, replace=False))
 
 
 def grf(m, seed=5, corr=0.1):
