@@ -184,3 +184,16 @@ def test_relative_residual_exact_values(dim, m, p):
     Eg = Ed.copy()
     Eg[s.D] = 1e6 * (1 + 1j)
     assert system.relative_residual(s, Eg) <= 1e-13
+
+
+def test_stored_3d_reference_solves_the_oracle_system():
+    """The stored 16^3 solution (tests/golden/make_c3_reference.py) is the oracle's: its relative
+    residual in the oracle's own assembled system of the 3D recipe is at rounding level."""
+    import os
+
+    import workloads
+    E = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c3_m16_oracle_E.npy"))
+    s = system.assemble(Problem(**dict(workloads.c3(16), subdomains=(1, 1, 1))))
+    assert E.shape == (s.n,)
+    assert system.relative_residual(s, E) <= 1e-13
+    assert np.array_equal(E[s.D], s.gD)
