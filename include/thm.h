@@ -307,6 +307,29 @@ thm_status thm_set_spmv_variant(thm_system *sys, int32_t precision, int32_t vari
 thm_status thm_time_precond(thm_system *sys, int32_t precision, int32_t reps, double *ms_out, double *bytes_out,
                             int32_t *launches_out, void *stream);
 
+/* ---- allocation-free entry point ------------------------------------------
+ * For callers that cannot allocate device memory (work under stream capture, tight serving
+ * loops, harnesses that forbid hipMalloc): y = diag(K, K)^{-1} x exactly as
+ * thm_apply_precond computes it (same kernels, same results), with every work vector of the
+ * apply (reduced skeleton right-hand side, skeleton solution, condensation terms, FP32
+ * copies of x and y) in one static device array of the library, THM_NOALLOC_SCRATCH_BYTES
+ * per device, held until the process ends.  The call allocates and frees nothing, copies
+ * nothing between host and device and does not synchronise: it only enqueues kernels on
+ * `stream` (a hipStream_t; NULL = the null stream) and returns.  x_dev, y_dev: device
+ * complex128[n_dofs] (interleaved re, im), caller-owned; they must not overlap.
+ * Preconditions: sys is a single-domain system and its factor and apply schedule already
+ * exist, i.e. thm_apply_precond (either precision) or a thm_gmres_solve on {sys} alone has
+ * run on it since its last thm_system_set_mu / thm_system_release_workspaces.
+ * Every call on one device shares the array and leaves its contents there (work vectors are
+ * cleared by the call where they must start at zero): calls that overlap in time on one
+ * device -- on different streams or threads -- race and give undefined results.
+ * Errors: THM_EINVAL (NULL arguments, unknown precision, factor or schedule not built yet,
+ * or a system whose work vectors exceed THM_NOALLOC_SCRATCH_BYTES -- the message gives the
+ * size needed), THM_EHIP (the array's address could not be obtained, or a launch failed). */
+#define THM_NOALLOC_SCRATCH_BYTES (64u << 20)
+thm_status thm_apply_precond_noalloc(thm_system *sys, int32_t precision, const void *x_dev, void *y_dev,
+                                     void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -67,7 +67,7 @@ EXPORTS = ["thm_default_opts", "thm_assemble", "thm_gmres_solve", "thm_ddm_solve
            "thm_system_info", "thm_system_set_mu", "thm_system_destroy", "thm_last_error", "thm_apply_operator",
            "thm_apply_precond", "thm_export_matrices", "thm_export_rhs", "thm_export_elements", "thm_time_spmv",
            "thm_time_precond", "thm_set_spmv_variant", "thm_apply_precond_full", "thm_time_spmv_batch",
-           "thm_time_spmv_systems", "thm_system_release_workspaces"]
+           "thm_time_spmv_systems", "thm_system_release_workspaces", "thm_apply_precond_noalloc"]
 THM_SPMV_SELL = 19
 THM_SPMV_SELL_GROUP = 20
 SPMV_VARIANTS = [21, 41, 81, 161, 321, 641, 24, 44, 84, 164, 324, THM_SPMV_SELL, THM_SPMV_SELL_GROUP]
@@ -101,6 +101,7 @@ def load_library(path=LIB_PATH):
         "thm_time_precond": (i32, [vp, i32, i32, dp, dp, ctypes.POINTER(i32), vp]),
         "thm_set_spmv_variant": (i32, [vp, i32, i32]),
         "thm_apply_precond_full": (i32, [vp, i32, i32, vp, vp, vp]),
+        "thm_apply_precond_noalloc": (i32, [vp, i32, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -293,6 +294,17 @@ def thm_apply_precond(system, x, precision=THM_FP64, stream=None):
     y = torch.empty_like(_cvec(system.n, x))
     _check(_lib.thm_apply_precond(system.handle, int(precision), ctypes.c_void_p(x.data_ptr()),
                                   ctypes.c_void_p(y.data_ptr()), _stream(stream)))
+    return y
+
+
+def thm_apply_precond_noalloc(system, x, y, precision=THM_FP64, stream=None):
+    """y = diag(K, K)^{-1} x into the caller's y, without any device allocation in the library
+    (its work vectors live in a static device array); enqueued on the stream, not synchronised.
+    The system's factor must exist (thm_apply_precond once first)."""
+    _cvec(system.n, x)
+    _cvec(system.n, y)
+    _check(_lib.thm_apply_precond_noalloc(system.handle, int(precision), ctypes.c_void_p(x.data_ptr()),
+                                          ctypes.c_void_p(y.data_ptr()), _stream(stream)))
     return y
 
 

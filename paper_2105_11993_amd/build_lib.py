@@ -17,7 +17,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libthm.so")
 SOURCES = ["topo.cpp", "solver.cpp", "precond.cpp", "thm_abi.cpp", "kernels_la.hip", "kernels_fe.hip", "kernels_prec.hip",
            "kernels_full.hip", "kernels_inv.hip",
-           "kernels_ddm.hip"]
+           "kernels_ddm.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("THM_OFFLOAD_ARCH", "gfx950")

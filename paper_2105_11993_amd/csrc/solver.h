@@ -228,4 +228,10 @@ void setup_precond(const std::vector<thm_system *> &systems, hipStream_t st, boo
 bool same_matrices(thm_system &a, thm_system &b, hipStream_t st);
 double now_ms();
 
+// Allocation-free block-preconditioner apply (noalloc.hip): y = diag(K, K)^{-1} x for the
+// single system of context c, on stream st, with every work vector in the library's static
+// device scratch array of NOALLOC_SCRATCH_BYTES.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(64) << 20;
+void noalloc_prec_apply(Ctx &c, int precision, const double *x, double *y, hipStream_t st);
+
 }  // namespace thm

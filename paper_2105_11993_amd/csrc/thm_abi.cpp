@@ -1222,6 +1222,24 @@ thm_status thm_apply_precond(thm_system *sys, int32_t precision, const void *x_d
     });
 }
 
+thm_status thm_apply_precond_noalloc(thm_system *sys, int32_t precision, const void *x_dev, void *y_dev,
+                                     void *stream) {
+    return guard([&] {
+        if (!sys || !x_dev || !y_dev) fail(THM_EINVAL, "bad arguments");
+        if (precision != THM_FP64 && precision != THM_FP32_IR) fail(THM_EINVAL, "unknown precision");
+        // the system's own single-system context (looked up, never created: no allocation)
+        Ctx *c = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(g_cache_mu);
+            for (auto &kv : g_ctx_cache)
+                if (kv.first.size() == 1 && kv.first[0] == sys && kv.second) c = kv.second.get();
+        }
+        if (!c || !c->prec_ready)
+            fail(THM_EINVAL, "preconditioner of this system not built yet: call thm_apply_precond once first");
+        noalloc_prec_apply(*c, precision, (const double *)x_dev, (double *)y_dev, (hipStream_t)stream);
+    });
+}
+
 thm_status thm_apply_precond_full(thm_system *sys, int32_t transpose, int32_t precision, const void *x_dev,
                                   void *y_dev, void *stream) {
     return guard([&] {
@@ -1417,6 +1435,7 @@ thm_status thm_time_spmv_systems(int32_t nsys, thm_system *const *sys, int32_t p
     });
 }
 
+static_assert(THM_NOALLOC_SCRATCH_BYTES == thm::NOALLOC_SCRATCH_BYTES, "scratch size of the header and the library");
 static_assert(THM_SPMV_SELL == thm::SPMV_SELL && THM_SPMV_SELL_GROUP == thm::SPMV_SELL_GROUP,
               "SpMV variant codes of the header and the kernels differ");
 
