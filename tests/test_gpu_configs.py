@@ -32,9 +32,12 @@ def test_c5_adjoint_full_size(thm):
     """128^2 quads, p = 1, w = 30, mu from the Gaussian random field: forward solve and the
     adjoint gradient (16,384 parameters) against the oracle's LU solve and exact gradient, and
     central differences of J (GPU solves) on all 32 seeded cells.  The differences use the
-    five-point central formula (8 (J(+h) - J(-h)) - (J(+2h) - J(-2h))) / 12h, h = 1e-5 mu_c:
-    the three-point formula's h^2 truncation term alone reaches 1e-6 of the metric on cells
-    whose derivative is near the metric's floor (measured 1.04e-6 on cell 11004)."""
+    five-point central formula (8 (J(+h) - J(-h)) - (J(+2h) - J(-2h))) / 12h with h = 1e-4 mu_c.
+    With h = 1e-5 mu_c the three-point formula's h^2 truncation term reaches 1e-6 of the metric
+    on cells whose derivative is near the metric's floor (1.04e-6 on cell 11004), and the
+    five-point one's rounding term does (1.3e-6 on the same cell: J carries a few ulp from the
+    1e-13 solves, divided by h); at h = 1e-4 mu_c the truncation term is below 1e-15 and the
+    rounding term near 1e-7."""
     import torch
     d = workloads.c5()
     print("case c5 full", flush=True)
@@ -56,7 +59,7 @@ def test_c5_adjoint_full_size(thm):
     mu0 = np.asarray(d["mu"], dtype=np.float64)
     worst = 0.0
     for c in cells:
-        h = 1e-5 * mu0[c]
+        h = 1e-4 * mu0[c]
         Js = {}
         for k in (2, 1, -1, -2):
             mu = mu0.copy()
@@ -88,26 +91,32 @@ def test_c4_uneven_batch_reduced(thm):
 
 def test_c3_ddm_8(thm):
     """3D recipe (mu ~ U[1,2] per cell, seed 3, w = 20, 2x2x2 subdomains) on 8^3 hexes
-    against the oracle's global LU."""
+    against the oracle's global LU, block preconditioner.  The outer interface GMRES of this
+    3D partition stagnates just above 1e-13 (3.2e-13 after 500 outer steps) and the mixed form
+    just above 1e-11, so the runs stop at 1e-12 (FP64) and 1e-10 (FP32 + refinement): errors
+    then measure 1e-12 and 2e-11 against the bars of 1e-10 and 1e-8."""
     d = workloads.c3(m=8)
     print("case c3 8^3", flush=True)
     S = thm.thm_assemble(d)
     Eg = system.solve_lu(system.assemble(problem(d)))
-    E, st = ddm_fp64(thm, S, restart=80)
+    E, st = ddm_fp64(thm, S, restart=80, rtol=1e-12)
     print("c3 8^3 fp64:", st, rel(E, Eg), flush=True)
-    assert st["rel_residual"] <= 1e-12
+    assert st["status"] == 0 and st["rel_residual"] <= 1e-12
     assert rel(E, Eg) <= 1e-10
-    E, st = ddm_mixed(thm, S, restart=80)
+    E, st = ddm_mixed(thm, S, restart=80, rtol=1e-10)
     print("c3 8^3 fp32+refinement:", st, rel(E, Eg), flush=True)
+    assert st["status"] == 0 and st["rel_residual"] <= 1e-10
     assert rel(E, Eg) <= 1e-8
 
 
 def test_c3_ddm_16(thm):
     """The 3D recipe on 16^3 hexes (104,544 DoFs, 2x2x2 subdomains of 8^3) against the oracle's
     solution stored by tests/golden/make_c3_reference.py (the oracle's global sparse LU with
-    refinement, residual checked <= 1e-13).  FP64 with the complete inverse of the subdomain
-    systems (fast; the field does not depend on the preconditioner) and FP32 + refinement with
-    the block preconditioner of eq. (11)."""
+    refinement, residual checked <= 1e-13).  Both forms precondition the subdomain solves with
+    the complete inverse of the subdomain systems (the field does not depend on the
+    preconditioner; with the block preconditioner of eq. (11) a 16^3 DDM solve takes minutes,
+    and that path is compared with the oracle at 8^3 above): FP64 to 1e-13, FP32 + refinement
+    to 1e-10 (the 3D outer iteration stagnates near 1e-11 in the mixed form)."""
     Eg = np.load(os.path.join(GOLDEN, "c3_m16_oracle_E.npy"))
     d = workloads.c3(m=16)
     print("case c3 16^3", flush=True)
@@ -117,9 +126,9 @@ def test_c3_ddm_16(thm):
     print("c3 16^3 fp64 (complete inverse):", st, rel(E, Eg), flush=True)
     assert st["rel_residual"] <= 1e-12
     assert rel(E, Eg) <= 1e-10
-    E, st = ddm_mixed(thm, S, restart=80)
-    print("c3 16^3 fp32+refinement (block):", st, rel(E, Eg), flush=True)
-    assert st["rel_residual"] <= 1e-10
+    E, st = ddm_mixed(thm, S, restart=80, rtol=1e-10, precond=thm.THM_PREC_FULL)
+    print("c3 16^3 fp32+refinement (complete inverse):", st, rel(E, Eg), flush=True)
+    assert st["status"] == 0 and st["rel_residual"] <= 1e-10
     assert rel(E, Eg) <= 1e-8
 
 
@@ -159,8 +168,9 @@ def test_c2_full_size(thm):
     """The benchmark configuration at full size (256^2 quads, degree 2, 1,181,184 DoFs, 4x4
     subdomains) against the oracle's global LU: the timed form (FP32 + refinement, relaxed
     subdomain tolerance, 1e-8) has an oracle-computed residual <= 1e-8 that agrees with the
-    library's own; FP64 to 1e-13 matches to 1e-10 and FP32 + refinement to 1e-11 matches to
-    1e-8."""
+    library's own; FP64 to 1e-12 matches to 1e-10 and FP32 + refinement to 1e-10 matches to
+    1e-8.  (The outer interface GMRES stagnates just below 1e-12 in FP64 and near 3e-11 in the
+    mixed form: 500 outer steps reach 9.5e-13 and 2.9e-11, with errors 3.3e-12 and 1.4e-10.)"""
     d = workloads.c2()
     print("case c2 full", flush=True)
     S = thm.thm_assemble(d)
@@ -174,17 +184,20 @@ def test_c2_full_size(thm):
     assert st["status"] == 0 and r <= 1e-8
     assert abs(r - st["rel_residual"]) <= 1e-3 * r
     assert rel(Eh[so.D], so.gD) <= 1e-13
-    E, st = ddm_fp64(thm, S, restart=64)
+    E, st = ddm_fp64(thm, S, restart=64, rtol=1e-12)
     print("c2 fp64:", st, rel(E, Eo), flush=True)
+    assert st["status"] == 0 and st["rel_residual"] <= 1e-12
     assert rel(E, Eo) <= 1e-10
-    E, st = ddm_mixed(thm, S, restart=64)
+    E, st = ddm_mixed(thm, S, restart=64, rtol=1e-10)
     print("c2 fp32+refinement:", st, rel(E, Eo), flush=True)
+    assert st["status"] == 0 and st["rel_residual"] <= 1e-10
     assert rel(E, Eo) <= 1e-8
 
 
 def test_refinement_fallback_is_fp64_accurate(thm):
-    """With no refinement steps allowed, every system is finished by FP64 GMRES from its
-    iterate: FP64 accuracy, and the stats report the fallback."""
+    """With no refinement steps allowed, every system is finished from its iterate by
+    GMRES-based refinement (FP64 GMRES preconditioned by the FP32 factor): FP64 accuracy, and
+    the stats report that path."""
     from tests._gpu_helpers import spec
     d = spec(2, 12, 2, 12.0)
     print("case forced fp64 finish", flush=True)
@@ -192,7 +205,7 @@ def test_refinement_fallback_is_fp64_accurate(thm):
     Eo = system.solve_lu(system.assemble(problem(d)))
     (E,), (st,) = thm.thm_gmres_solve([S], thm.default_opts(rtol=1e-13, restart=40, precision=thm.THM_FP32_IR,
                                                             max_refine=0))
-    assert st["status"] == 0 and st["fp64_fallback"] == 1
+    assert st["status"] == 0 and st["gmres_ir"] == 1 and st["fp64_fallback"] == 0
     assert rel(E.cpu().numpy(), Eo) <= 1e-10
 
 
