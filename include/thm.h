@@ -65,14 +65,16 @@ typedef enum { THM_KRYLOV_COMPLEX = 0, THM_KRYLOV_REAL = 1 } thm_krylov;
  * Supported for r <= 4096 per subdomain (THM_EUNSUPPORTED above: the setup inverts the
  * dense 2r x 2r real form of M). */
 typedef enum { THM_PREC_BLOCK = 0, THM_PREC_FULL = 1 } thm_precond;
-/* How THM_FP32_IR refines (block preconditioner).  THM_IR_CLASSIC: FP64 residuals, each correction
- * by one cycle of FP32 GMRES (FP32 operator, basis and factor); a step that does not halve a
- * system's FP64 residual is undone and that system continues by GMRES-based refinement, as do
- * its later solves in the same batch (until its matrices change).
+/* How THM_FP32_IR refines (either preconditioner).  THM_IR_CLASSIC: FP64 residuals, each
+ * correction by one cycle of FP32 GMRES (FP32 operator, basis and preconditioner); a step that
+ * does not halve a system's FP64 residual is undone and that system continues by GMRES-based
+ * refinement, as do its later solves with the same preconditioner in the same batch (until its
+ * matrices change).
  * THM_IR_GMRES: GMRES-based refinement from the start (Carson and Higham's GMRES-IR: the
  * correction is solved by FP64 GMRES -- FP64 operator, basis and Hessenberg -- preconditioned by
- * the FP32 factor, so the factor's accuracy limits only the convergence rate).  Either way a
- * system GMRES-IR leaves above rtol is finished by FP64 GMRES with the FP64 factor. */
+ * the FP32 preconditioner, block or complete inverse, so its accuracy limits only the
+ * convergence rate).  Either way a system GMRES-IR leaves above rtol is finished by FP64 GMRES
+ * with the FP64 preconditioner. */
 typedef enum { THM_IR_CLASSIC = 0, THM_IR_GMRES = 1 } thm_ir_mode;
 
 /* Problem statement (paper Sec. 2, eq. (1); partition eq. (5)).  Copied by thm_assemble. */

@@ -132,13 +132,17 @@ void launch_norm_finish(const Batch &B, const double *part, const int32_t *mask,
                         double rtol, double *resid, int32_t *running, hipStream_t st);
 void launch_reduce_cols(const Batch &B, const int32_t *mask, const int32_t *jcnt, int ncols_fixed,
                         const double *part, double *out, int ldo, int accumulate, hipStream_t st);
+// Start of a cycle: tolerance read from rtol_d; resets *step_ctr (if non-null); writes each
+// system's running flag to hrun (host-visible, may be null).
 void launch_cycle_start(const Batch &B, const double *part, int32_t *running, int32_t *active, int32_t *jcnt,
-                        const double *bnorm, double rtol, double *g, int m, double *beta, double *resid,
-                        int32_t *iters, int max_iter, hipStream_t st);
+                        const double *bnorm, const double *rtol_d, double *g, int m, double *beta, double *resid,
+                        int32_t *iters, int max_iter, int32_t *step_ctr, int32_t *hrun, hipStream_t st);
+// End of an Arnoldi step: the flags go to host slot (step / spc) mod nslots.
 void launch_arnoldi_finish(const Batch &B, const double *part, int32_t *active, int32_t *jcnt, const double *hcol,
                            int ldh, double *H, double *cs, double *sn, double *g, double *hnext,
                            const double *bnorm, const double *rtol_d, int m, int32_t *iters, int max_iter,
-                           double *est, int32_t *hflags, const int32_t *step_ctr, int nslots, hipStream_t st);
+                           double *est, int32_t *hflags, const int32_t *step_ctr, int spc, int nslots,
+                           hipStream_t st);
 void launch_hsolve(const Batch &B, const int32_t *running, const int32_t *jcnt, const double *H, const double *g,
                    double *y, int m, hipStream_t st);
 template <class T>
@@ -257,10 +261,12 @@ struct FullDesc {
     const int64_t *moff = nullptr;   // complex offset of the system's M^{-1} (shared by identical systems)
     const void *m64 = nullptr, *m32 = nullptr;  // M^{-1}, complex column-major
 };
-void launch_full_unit(const FullDesc &F, int ns, const int32_t *mask, const int64_t *off, int k, double val,
-                      double *x, hipStream_t st);
-void launch_full_gather(const FullDesc &F, int ns, const int32_t *mask, const int64_t *off, int k,
-                        const double *z, const int64_t *soff, double *S, hipStream_t st);
+// Setup of S_G: unit vectors at Gamma entries 2k, 2k + 1 and the gather of the matching
+// columns of K^{-1}; k = k0 + kadd[s] per system (kadd null: k0).
+void launch_full_unit(const FullDesc &F, int ns, const int32_t *mask, const int64_t *off, const int32_t *kadd,
+                      int k0, double val, double *x, hipStream_t st);
+void launch_full_gather(const FullDesc &F, int ns, const int32_t *mask, const int64_t *off, const int32_t *kadd,
+                        int k0, const double *z, const int64_t *soff, double *S, hipStream_t st);
 void launch_full_block(int r, const double *S, const int32_t *cptr, const int32_t *ccol, const double *cval,
                        double *Bm, hipStream_t st);
 void launch_full_extract(int r, const double *Inv, double *M64, float *M32, hipStream_t st);

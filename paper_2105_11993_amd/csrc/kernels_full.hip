@@ -19,27 +19,31 @@
 namespace thm {
 
 // ------------------------------------------------------------------ setup
-// x[gamma_s[2k]].re = val, x[gamma_s[2k + 1]].im = val for every selected system.
+// x[gamma_s[2k]].re = val, x[gamma_s[2k + 1]].im = val for every selected system, with
+// k = k0 + kadd[s] (kadd may be null: k = k0).
 __global__ void k_full_unit(int ns, const int32_t *__restrict__ mask, const int64_t *__restrict__ goff,
-                            const int32_t *__restrict__ gam, const int64_t *__restrict__ off, int k, double val,
-                            double *__restrict__ x) {
+                            const int32_t *__restrict__ gam, const int64_t *__restrict__ off,
+                            const int32_t *__restrict__ kadd, int k0, double val, double *__restrict__ x) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= ns || (mask && !mask[s])) return;
     const int64_t g0 = goff[s], r = goff[s + 1] - g0;
+    const int64_t k = k0 + (kadd ? kadd[s] : 0);
     if (2 * k < r) x[off[s] + 2 * (int64_t)gam[g0 + 2 * k]] = val;
     if (2 * k + 1 < r) x[off[s] + 2 * (int64_t)gam[g0 + 2 * k + 1] + 1] = val;
 }
 
-// Columns 2k and 2k + 1 of S_G (column-major r x r at soff[s]) from z = K^{-1} x.
+// Columns 2k and 2k + 1 of S_G (column-major r x r at soff[s]) from z = K^{-1} x, with
+// k = k0 + kadd[s] as above.
 __global__ void k_full_gather(int ns, const int32_t *__restrict__ mask, const int64_t *__restrict__ goff,
-                              const int32_t *__restrict__ gam, const int64_t *__restrict__ off, int k,
-                              const double *__restrict__ z, const int64_t *__restrict__ soff,
-                              double *__restrict__ S) {
+                              const int32_t *__restrict__ gam, const int64_t *__restrict__ off,
+                              const int32_t *__restrict__ kadd, int k0, const double *__restrict__ z,
+                              const int64_t *__restrict__ soff, double *__restrict__ S) {
     const int s = blockIdx.y;
     if (mask && !mask[s]) return;
     const int64_t g0 = goff[s], r = goff[s + 1] - g0;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= r) return;
+    const int64_t k = k0 + (kadd ? kadd[s] : 0);
     const double *zs = z + off[s] + 2 * (int64_t)gam[g0 + i];
     double *Ss = S + soff[s];
     if (2 * k < r) Ss[(2 * k) * r + i] = zs[0];
@@ -168,16 +172,17 @@ __global__ void __launch_bounds__(256) k_full_fin(int ns, const int32_t *__restr
 }
 
 // ------------------------------------------------------------------ launchers
-void launch_full_unit(const FullDesc &F, int ns, const int32_t *mask, const int64_t *off, int k, double val,
-                      double *x, hipStream_t st) {
-    k_full_unit<<<(ns + 63) / 64, 64, 0, st>>>(ns, mask, F.goff, F.gam, off, k, val, x);
+void launch_full_unit(const FullDesc &F, int ns, const int32_t *mask, const int64_t *off, const int32_t *kadd,
+                      int k, double val, double *x, hipStream_t st) {
+    k_full_unit<<<(ns + 63) / 64, 64, 0, st>>>(ns, mask, F.goff, F.gam, off, kadd, k, val, x);
     THM_HIP(hipGetLastError());
 }
 
-void launch_full_gather(const FullDesc &F, int ns, const int32_t *mask, const int64_t *off, int k,
-                        const double *z, const int64_t *soff, double *S, hipStream_t st) {
+void launch_full_gather(const FullDesc &F, int ns, const int32_t *mask, const int64_t *off, const int32_t *kadd,
+                        int k, const double *z, const int64_t *soff, double *S, hipStream_t st) {
     if (!F.maxr || !ns) return;
-    k_full_gather<<<dim3((F.maxr + 255) / 256, ns), 256, 0, st>>>(ns, mask, F.goff, F.gam, off, k, z, soff, S);
+    k_full_gather<<<dim3((F.maxr + 255) / 256, ns), 256, 0, st>>>(ns, mask, F.goff, F.gam, off, kadd, k, z, soff,
+                                                                  S);
     THM_HIP(hipGetLastError());
 }
 

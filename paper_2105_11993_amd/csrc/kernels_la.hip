@@ -621,18 +621,28 @@ __device__ __forceinline__ double slot_sum(const double *part, int maxcols, int 
 }
 
 // Start of a GMRES cycle (one wave per system): beta = ||r||; systems with
-// beta/bnorm <= rtol stop; otherwise g = (beta, 0, ...), jcnt = 0, active = 1.
+// beta/bnorm <= rtol stop; otherwise g = (beta, 0, ...), jcnt = 0, active = 1.  The
+// tolerance is read from device memory (the launch may be replayed from a graph); the
+// step counter of the cycle is reset; each system's running flag is also written to
+// host-visible memory (hrun, may be null).
 __global__ void k_cycle_start(int ns, const int32_t *__restrict__ blkoff, const double *__restrict__ part,
                               int maxcols, int32_t *__restrict__ running, int32_t *__restrict__ active,
-                              int32_t *__restrict__ jcnt, const double *__restrict__ bnorm, double rtol,
-                              double *__restrict__ g, int m, double *__restrict__ beta_out,
-                              double *__restrict__ resid_out, int32_t *__restrict__ iters, int max_iter) {
+                              int32_t *__restrict__ jcnt, const double *__restrict__ bnorm,
+                              const double *__restrict__ rtol_d, double *__restrict__ g, int m,
+                              double *__restrict__ beta_out, double *__restrict__ resid_out,
+                              int32_t *__restrict__ iters, int max_iter, int32_t *__restrict__ step_ctr,
+                              int32_t *__restrict__ hrun) {
     const int s = blockIdx.x;
     if (s >= ns) return;
+    if (s == 0 && threadIdx.x == 0 && step_ctr) *step_ctr = 0;
     if (!running[s]) {
-        if (threadIdx.x == 0) active[s] = 0;
+        if (threadIdx.x == 0) {
+            active[s] = 0;
+            if (hrun) hrun[s] = 0;
+        }
         return;
     }
+    const double rtol = *rtol_d;
     const double beta = sqrt(slot_sum(part, maxcols, blkoff[s], blkoff[s + 1], 0));
     double *gs = g + (int64_t)s * 2 * (m + 1);
     for (int i = threadIdx.x; i < 2 * (m + 1); i += blockDim.x) gs[i] = 0.0;
@@ -644,9 +654,11 @@ __global__ void k_cycle_start(int ns, const int32_t *__restrict__ blkoff, const 
     if (!(rel > rtol) || iters[s] >= max_iter || !isfinite(rel)) {
         running[s] = 0;
         active[s] = 0;
+        if (hrun) hrun[s] = 0;
         return;
     }
     active[s] = 1;
+    if (hrun) hrun[s] = 1;
     gs[0] = beta;
 }
 
@@ -660,12 +672,13 @@ __global__ void k_arnoldi_finish(int ns, const int32_t *__restrict__ blkoff, con
                                  double *__restrict__ hnext, const double *__restrict__ bnorm,
                                  const double *__restrict__ rtol_d, int m, int32_t *__restrict__ iters, int max_iter,
                                  double *__restrict__ resid_est, int32_t *__restrict__ hflags,
-                                 const int32_t *__restrict__ step_ctr, int nslots) {
+                                 const int32_t *__restrict__ step_ctr, int spc, int nslots) {
     __shared__ double colr[1025], coli[1025], csl[1024], snr[1024], sni[1024];
     const int s = blockIdx.x;
     if (s >= ns) return;
-    // the system's flag after this step, also written to host memory (slot of the step)
-    int32_t *hf = hflags + (int64_t)(*step_ctr % nslots) * ns + s;
+    // the system's flag after this step, also written to host memory (one slot per group of
+    // spc consecutive steps: the last step of the group leaves its flag there)
+    int32_t *hf = hflags + (int64_t)((*step_ctr / spc) % nslots) * ns + s;
     if (!active[s]) {
         if (threadIdx.x == 0) *hf = 0;
         return;
@@ -871,20 +884,21 @@ void launch_reduce_cols(const Batch &B, const int32_t *mask, const int32_t *jcnt
     THM_HIP(hipGetLastError());
 }
 void launch_cycle_start(const Batch &B, const double *part, int32_t *running, int32_t *active, int32_t *jcnt,
-                        const double *bnorm, double rtol, double *g, int m, double *beta, double *resid,
-                        int32_t *iters, int max_iter, hipStream_t st) {
-    k_cycle_start<<<B.ns, 64, 0, st>>>(B.ns, B.vs.blkoff.p, part, B.maxcols, running, active, jcnt,
-                                                   bnorm, rtol, g, m, beta, resid, iters, max_iter);
+                        const double *bnorm, const double *rtol_d, double *g, int m, double *beta, double *resid,
+                        int32_t *iters, int max_iter, int32_t *step_ctr, int32_t *hrun, hipStream_t st) {
+    k_cycle_start<<<B.ns, 64, 0, st>>>(B.ns, B.vs.blkoff.p, part, B.maxcols, running, active, jcnt, bnorm, rtol_d,
+                                       g, m, beta, resid, iters, max_iter, step_ctr, hrun);
     THM_HIP(hipGetLastError());
 }
 void launch_arnoldi_finish(const Batch &B, const double *part, int32_t *active, int32_t *jcnt, const double *hcol,
                            int ldh, double *H, double *cs, double *sn, double *g, double *hnext,
                            const double *bnorm, const double *rtol_d, int m, int32_t *iters, int max_iter,
-                           double *est, int32_t *hflags, const int32_t *step_ctr, int nslots, hipStream_t st) {
+                           double *est, int32_t *hflags, const int32_t *step_ctr, int spc, int nslots,
+                           hipStream_t st) {
     if (m > 1024) fail(THM_EINVAL, "restart must be <= 1024");
     k_arnoldi_finish<<<B.ns, 64, 0, st>>>(B.ns, B.vs.blkoff.p, part, B.maxcols, active, jcnt, hcol,
                                                       ldh, H, cs, sn, g, hnext, bnorm, rtol_d, m, iters, max_iter,
-                                                      est, hflags, step_ctr, nslots);
+                                                      est, hflags, step_ctr, spc, nslots);
     THM_HIP(hipGetLastError());
 }
 void launch_hsolve(const Batch &B, const int32_t *running, const int32_t *jcnt, const double *H, const double *g,

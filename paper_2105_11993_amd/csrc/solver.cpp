@@ -46,9 +46,11 @@ void Krylov::init(const std::vector<int64_t> &n, int m_, hipStream_t st) {
     part.alloc((size_t)std::max(1, B.vs.nblocks) * NPW * B.maxcols);
     for (DBuf<int32_t> *b : {&running, &active, &jcnt, &iters}) b->alloc(ns);
     if (pinned) (void)hipHostFree(pinned);
-    THM_HIP(hipHostMalloc((void **)&pinned, sizeof(int32_t) * NEV * std::max(ns, 1),
+    THM_HIP(hipHostMalloc((void **)&pinned, sizeof(int32_t) * (NEV + 1) * std::max(ns, 1),
                           hipHostMallocMapped | hipHostMallocCoherent));
     THM_HIP(hipHostGetDevicePointer((void **)&pinned_dev, pinned, 0));
+    pinned_run = pinned + (size_t)NEV * std::max(ns, 1);
+    pinned_run_dev = pinned_dev + (size_t)NEV * std::max(ns, 1);
     step_ctr.alloc(1);
     for (auto &e : ev)
         if (!e) THM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -81,11 +83,12 @@ void Krylov::ensure<float>(hipStream_t) {
 }
 
 void Krylov::drop_graphs() {
-    for (auto &s : slots) {
-        if (s.exec) (void)hipGraphExecDestroy(s.exec);
-        if (s.graph) (void)hipGraphDestroy(s.graph);
-        s = GraphSlot{};
-    }
+    for (auto &row : slots)
+        for (auto &s : row) {
+            if (s.exec) (void)hipGraphExecDestroy(s.exec);
+            if (s.graph) (void)hipGraphDestroy(s.graph);
+            s = GraphSlot{};
+        }
 }
 
 Krylov::~Krylov() {
@@ -101,7 +104,7 @@ template <> struct TypeKey<double> { static constexpr int v = 0; };
 template <> struct TypeKey<float> { static constexpr int v = 1; };
 
 template <class T>
-static void arnoldi_step(Krylov &K, const KOps<T> &ops, const GmresParams &p, hipStream_t st) {
+static void arnoldi_step(Krylov &K, const KOps<T> &ops, const GmresParams &p, int spc, hipStream_t st) {
     Batch &B = K.B;
     const int m = K.m;
     T *V = K.V<T>(), *w = K.w<T>(), *z = K.z<T>(), *cur = K.cur<T>();
@@ -119,24 +122,58 @@ static void arnoldi_step(Krylov &K, const KOps<T> &ops, const GmresParams &p, hi
         launch_cgs_update<T>(B, act, K.jcnt.p, V, B.Ltot, w, K.hcol2.p, ldh, K.part.p, st);
     }
     launch_arnoldi_finish(B, K.part.p, act, K.jcnt.p, K.hcol.p, ldh, K.H.p, K.cs.p, K.sn.p, K.g.p, K.hnext.p,
-                          K.bnorm.p, K.rtol_d.p, m, K.iters.p, p.max_iter, K.est.p, K.pinned_dev, K.step_ctr.p,
+                          K.bnorm.p, K.rtol_d.p, m, K.iters.p, p.max_iter, K.est.p, K.pinned_dev, K.step_ctr.p, spc,
                           Krylov::NEV, st);
     launch_scale<T, T>(B, act, K.hnext.p, 1, w, V, K.jcnt.p, B.Ltot, cur, st, K.step_ctr.p);
 }
 
+// Start of a cycle: w = b - A x, beta = ||w||, stop test (running flags to host memory),
+// V_0 = cur = w / beta, step counter reset.
 template <class T>
-static hipGraphExec_t step_graph(Krylov &K, const KOps<T> &ops, const GmresParams &p, hipStream_t st) {
-    const int key = TypeKey<T>::v * 2 + (ops.csign < 0 ? 1 : 0) + (ops.pkind == 2 ? 4 : 0);
-    Krylov::GraphSlot &s = K.slots[key];
+static void cycle_open(Krylov &K, const KOps<T> &ops, const GmresParams &p, const T *b, const T *x,
+                       hipStream_t st) {
+    Batch &B = K.B;
+    T *V = K.V<T>(), *w = K.w<T>(), *cur = K.cur<T>();
+    ops.apply(x, w, b, K.running.p);
+    launch_norm2<T>(B, K.running.p, w, K.part.p, st);
+    launch_cycle_start(B, K.part.p, K.running.p, K.active.p, K.jcnt.p, K.bnorm.p, K.rtol_d.p, K.g.p, K.m,
+                       K.beta.p, K.resid.p, K.iters.p, p.max_iter, K.step_ctr.p, K.pinned_run_dev, st);
+    launch_scale<T, T>(B, K.active.p, K.beta.p, 1, w, V, K.jcnt.p, B.Ltot, cur, st);
+}
+
+// End of a cycle: y = H^{-1} g, x += P^{-1} (V y).
+template <class T>
+static void cycle_close(Krylov &K, const KOps<T> &ops, T *x, hipStream_t st) {
+    Batch &B = K.B;
+    T *V = K.V<T>(), *z = K.z<T>(), *cur = K.cur<T>();
+    launch_hsolve(B, K.running.p, K.jcnt.p, K.H.p, K.g.p, K.y.p, K.m, st);
+    launch_lincomb<T>(B, K.running.p, K.jcnt.p, V, B.Ltot, K.y.p, 2 * (K.m + 1), cur, st);
+    ops.prec(cur, z, K.running.p);
+    launch_axpy<T, T>(B, K.running.p, nullptr, z, x, st);
+}
+
+// Captured once per (precision, operator, options, kind, vectors) and replayed: kind 0 is a
+// chunk of GRAPH_SPC Arnoldi steps, kind 1 closes a cycle and opens the next (b and x are
+// part of the key, their addresses being baked into the graph).
+template <class T>
+static hipGraphExec_t cycle_graph(Krylov &K, const KOps<T> &ops, const GmresParams &p, int kind, const T *b, T *x,
+                                  hipStream_t st) {
+    const int key = TypeKey<T>::v * 2 + (ops.csign < 0 ? 1 : 0) + (ops.pkind >= 2 ? 4 : 0);
+    Krylov::GraphSlot &s = K.slots[key][kind];
     if (s.exec && s.owner == ops.owner && s.orth == p.orth && s.max_iter == p.max_iter && s.cplx == p.cplx &&
-        s.pkind == ops.pkind)
+        s.pkind == ops.pkind && (kind == 0 || (s.b == (const void *)b && s.x == (const void *)x)))
         return s.exec;
     if (s.exec) (void)hipGraphExecDestroy(s.exec);
     if (s.graph) (void)hipGraphDestroy(s.graph);
     s = Krylov::GraphSlot{};
     THM_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     try {
-        arnoldi_step<T>(K, ops, p, st);
+        if (kind == 0) {
+            for (int i = 0; i < Krylov::GRAPH_SPC; ++i) arnoldi_step<T>(K, ops, p, Krylov::GRAPH_SPC, st);
+        } else {
+            cycle_close<T>(K, ops, x, st);
+            cycle_open<T>(K, ops, p, b, x, st);
+        }
     } catch (...) {
         hipGraph_t g;
         (void)hipStreamEndCapture(st, &g);
@@ -153,10 +190,12 @@ static hipGraphExec_t step_graph(Krylov &K, const KOps<T> &ops, const GmresParam
     s.pkind = ops.pkind;
     s.csign = ops.csign;
     s.key_T = TypeKey<T>::v;
+    s.b = b;
+    s.x = x;
     return s.exec;
 }
 
-static bool any_set(const int32_t *h, int ns) {
+static bool any_set(const volatile int32_t *h, int ns) {
     for (int i = 0; i < ns; ++i)
         if (h[i]) return true;
     return false;
@@ -168,7 +207,6 @@ void gmres_run(Krylov &K, const KOps<T> &ops, const T *b, T *x, const int32_t *m
     Batch &B = K.B;
     const int ns = B.ns, m = K.m;
     K.ensure<T>(st);
-    T *V = K.V<T>(), *w = K.w<T>(), *z = K.z<T>(), *cur = K.cur<T>();
     launch_norm2<T>(B, mask_in, b, K.part.p, st);
     launch_norm_finish(B, K.part.p, mask_in, K.bnorm.p, nullptr, 0.0, nullptr, nullptr, st);
     THM_HIP(hipMemcpyAsync(K.running.p, mask_in, sizeof(int32_t) * ns, hipMemcpyDeviceToDevice, st));
@@ -176,37 +214,52 @@ void gmres_run(Krylov &K, const KOps<T> &ops, const T *b, T *x, const int32_t *m
     K.rtol_h = p.rtol;
     THM_HIP(hipMemcpyAsync(K.rtol_d.p, &K.rtol_h, sizeof(double), hipMemcpyHostToDevice, st));
     const bool graph = p.use_graph && ops.graphable;
-    hipGraphExec_t exec = graph ? step_graph<T>(K, ops, p, st) : nullptr;
-    int32_t *hflag[1] = {K.pinned};
-    for (;;) {
-        ops.apply(x, w, b, K.running.p);
-        launch_norm2<T>(B, K.running.p, w, K.part.p, st);
-        launch_cycle_start(B, K.part.p, K.running.p, K.active.p, K.jcnt.p, K.bnorm.p, p.rtol, K.g.p, m, K.beta.p,
-                           K.resid.p, K.iters.p, p.max_iter, st);
-        THM_HIP(hipMemcpyAsync(hflag[0], K.running.p, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, st));
-        THM_HIP(hipStreamSynchronize(st));
-        if (!any_set(hflag[0], ns)) break;
-        launch_scale<T, T>(B, K.active.p, K.beta.p, 1, w, V, K.jcnt.p, B.Ltot, cur, st);
-        // Arnoldi steps; the finish kernel of step j writes the systems' flags to host slot
-        // j mod NEV, and the host checks the flags of step j - LAG while later steps run.
-        THM_HIP(hipMemsetAsync(K.step_ctr.p, 0, sizeof(int32_t), st));
-        constexpr int LAG = 3;
-        static_assert(LAG + 1 < Krylov::NEV, "flag slots in flight must not wrap");
-        for (int step = 0; step < m; ++step) {
-            if (exec) THM_HIP(hipGraphLaunch(exec, st));
-            else arnoldi_step<T>(K, ops, p, st);
-            const int sl = step % Krylov::NEV;
-            THM_HIP(hipEventRecord(K.ev[sl], st));
-            if (step >= LAG) {
-                const int ol = (step - LAG) % Krylov::NEV;
+    if (!graph) {
+        // host-driven: one launch sequence per Arnoldi step; the finish kernel of step j writes
+        // the systems' flags to host slot j mod NEV, and the host checks the flags of step
+        // j - LAG while later steps run
+        for (;;) {
+            cycle_open<T>(K, ops, p, b, x, st);
+            THM_HIP(hipStreamSynchronize(st));
+            if (!any_set(K.pinned_run, ns)) break;
+            constexpr int LAG = 3;
+            static_assert(LAG + 1 < Krylov::NEV, "flag slots in flight must not wrap");
+            for (int step = 0; step < m; ++step) {
+                arnoldi_step<T>(K, ops, p, 1, st);
+                const int sl = step % Krylov::NEV;
+                THM_HIP(hipEventRecord(K.ev[sl], st));
+                if (step >= LAG) {
+                    const int ol = (step - LAG) % Krylov::NEV;
+                    THM_HIP(hipEventSynchronize(K.ev[ol]));
+                    if (!any_set(K.pinned + (size_t)ol * ns, ns)) break;
+                }
+            }
+            cycle_close<T>(K, ops, x, st);
+        }
+        return;
+    }
+    // graph replay: a cycle is ceil(m / GRAPH_SPC) chunk graphs (steps past a system's end
+    // of cycle find it inactive and do nothing) and one close-and-reopen graph.  The finish
+    // kernels of chunk c leave the systems' flags in host slot c mod NEV; the host checks
+    // chunk c - 1 while chunk c runs, and the running flags once per cycle.
+    hipGraphExec_t chunk = cycle_graph<T>(K, ops, p, 0, b, x, st);
+    hipGraphExec_t turn = cycle_graph<T>(K, ops, p, 1, b, x, st);
+    cycle_open<T>(K, ops, p, b, x, st);
+    THM_HIP(hipStreamSynchronize(st));
+    const int nchunks = (m + Krylov::GRAPH_SPC - 1) / Krylov::GRAPH_SPC;
+    static_assert(Krylov::NEV >= 4, "chunk flag slots in flight must not wrap");
+    while (any_set(K.pinned_run, ns)) {
+        for (int c = 0; c < nchunks; ++c) {
+            THM_HIP(hipGraphLaunch(chunk, st));
+            THM_HIP(hipEventRecord(K.ev[c % Krylov::NEV], st));
+            if (c >= 1) {
+                const int ol = (c - 1) % Krylov::NEV;
                 THM_HIP(hipEventSynchronize(K.ev[ol]));
                 if (!any_set(K.pinned + (size_t)ol * ns, ns)) break;
             }
         }
-        launch_hsolve(B, K.running.p, K.jcnt.p, K.H.p, K.g.p, K.y.p, m, st);
-        launch_lincomb<T>(B, K.running.p, K.jcnt.p, V, B.Ltot, K.y.p, 2 * (m + 1), cur, st);
-        ops.prec(cur, z, K.running.p);
-        launch_axpy<T, T>(B, K.running.p, nullptr, z, x, st);
+        THM_HIP(hipGraphLaunch(turn, st));
+        THM_HIP(hipStreamSynchronize(st));
     }
 }
 
@@ -231,7 +284,7 @@ void bcr_chunk_table(const BcrTask &t, std::vector<int32_t> &out) {
 }
 
 // ------------------------------------------------------------------ batched context
-void Ctx::build(const std::vector<thm_system *> &s, int m, hipStream_t stream) {
+void Ctx::build(const std::vector<thm_system *> &s, int m, hipStream_t stream, bool spmv_setup) {
     sys = s;
     ns = (int)s.size();
     st = stream;
@@ -263,6 +316,7 @@ void Ctx::build(const std::vector<thm_system *> &s, int m, hipStream_t stream) {
     bnorm64.alloc(ns);
     resid64.alloc(ns);
     THM_HIP(hipStreamSynchronize(st));
+    if (!spmv_setup) return;
     build_groups();
     autotune();
 }
@@ -623,10 +677,10 @@ void Ctx::build_full() {
             moff[s] = moff[rep[s]];
         }
     }
-    // M is inverted by the unblocked Gauss-Jordan of the setup (a rank-1 update of the whole
-    // 2r x 2r matrix per column, 16 (2r)^3 bytes of traffic): bounded to keep setup in seconds
-    if (maxr_rep > 4096)
-        fail(THM_EUNSUPPORTED, "boundary set too large for the complete inverse (more than 4096 DoFs carry C)");
+    // M is inverted densely in its real 2r x 2r form: bounded so that one inversion's three
+    // buffers stay within 3 x 8 GiB and its 16 r^3 flops within a minute
+    if (maxr_rep > 16384)
+        fail(THM_EUNSUPPORTED, "boundary set too large for the complete inverse (more than 16384 DoFs carry C)");
     std::vector<float> cval32(cval.begin(), cval.end());
     full.goff.upload(goff, st);
     full.gam.upload(gam.empty() ? std::vector<int32_t>{0} : gam, st);
@@ -650,51 +704,100 @@ void Ctx::build_full() {
     d.m64 = full.m64.p;
     d.m32 = full.m32.p;
     if (maxr_rep > 0) {
-        // S_G: columns 2k, 2k + 1 of every representative from one batched FP64 application
-        DBuf<double> Sg(std::max<int64_t>(mtot, 1)), xin(K.B.Ltot), zout(K.B.Ltot);
-        DBuf<int64_t> dsoff;
-        dsoff.upload(soff, st);
-        DBuf<int32_t> dmask;
-        dmask.upload(isrep, st);
-        THM_HIP(hipMemsetAsync(xin.p, 0, sizeof(double) * xin.n, st));
-        for (int64_t k = 0; 2 * k < maxr_rep; ++k) {
-            launch_full_unit(d, ns, dmask.p, K.B.off.p, (int)k, 1.0, xin.p, st);
-            launch_prec_apply<double>(P, P.d64.p, K.B.off.p, ns, dmask.p, xin.p, zout.p, ws64.p, ys64.p, tw64.p, st);
-            launch_full_gather(d, ns, dmask.p, K.B.off.p, (int)k, zout.p, dsoff.p, Sg.p, st);
-            launch_full_unit(d, ns, dmask.p, K.B.off.p, (int)k, 0.0, xin.p, st);
-        }
-        // M = I + i C_G S_G in real form, inverted by Gauss-Jordan, then stored complex
-        std::vector<int> reps;
-        int64_t btot = 0;
-        for (int s = 0; s < ns; ++s)
-            if (isrep[s]) {
-                reps.push_back(s);
-                btot += 4 * full.r[s] * full.r[s];
+        // S_G: K^{-1} applied to unit vectors on Gamma, columns 2k and 2k + 1 from the real and
+        // imaginary parts of one right-hand side.  A temporary batch holds Q copies of every
+        // representative; the copies share its factor and form one member group of the apply,
+        // so one FP64 application yields 2Q columns of every representative while each factor
+        // matrix is read once per 16 copies.
+        DBuf<double> Sg(std::max<int64_t>(mtot, 1));
+        {
+            const int Q = (int)std::min<int64_t>(16, (maxr_rep + 1) / 2);
+            std::vector<thm_system *> tsys;
+            std::vector<int64_t> tgoff(1, 0), tsoff;
+            std::vector<int32_t> tgam, tk;
+            for (int s = 0; s < ns; ++s) {
+                if (!isrep[s]) continue;
+                for (int q = 0; q < Q; ++q) {
+                    tsys.push_back(sys[s]);
+                    tgam.insert(tgam.end(), gam.begin() + goff[s], gam.begin() + goff[s + 1]);
+                    tgoff.push_back((int64_t)tgam.size());
+                    tsoff.push_back(soff[s]);
+                    tk.push_back(q);
+                }
             }
-        DBuf<double> Bm(btot), Inv(btot), Wk(btot);
-        DBuf<int32_t> piv(std::max<int64_t>(4 * maxr_rep * (int64_t)reps.size(), 1)), status(1);
-        THM_HIP(hipMemsetAsync(status.p, 0, sizeof(int32_t), st));
-        std::vector<InvDesc> jobs;
-        int64_t bo = 0;
-        for (size_t q = 0; q < reps.size(); ++q) {
-            const int s = reps[q];
-            const int r = (int)full.r[s];
-            launch_full_block(r, Sg.p + soff[s], full.cptr.p + goff[s], full.ccol.p, full.cval64.p, Bm.p + bo, st);
-            jobs.push_back({2 * r, Bm.p + bo, Wk.p + bo, Inv.p + bo, piv.p + 4 * maxr_rep * (int64_t)q, 2 * r});
-            bo += 4 * (int64_t)r * r;
+            Ctx T;
+            T.build(tsys, 1, st, false);
+            T.build_prec();
+            DBuf<int64_t> dtgoff, dtsoff;
+            DBuf<int32_t> dtgam, dtk;
+            dtgoff.upload(tgoff, st);
+            dtsoff.upload(tsoff, st);
+            dtgam.upload(tgam, st);
+            dtk.upload(tk, st);
+            FullDesc td = d;
+            td.goff = dtgoff.p;
+            td.gam = dtgam.p;
+            DBuf<double> xin(T.K.B.Ltot), zout(T.K.B.Ltot);
+            THM_HIP(hipMemsetAsync(xin.p, 0, sizeof(double) * xin.n, st));
+            const int nt = T.ns;
+            for (int64_t k = 0; 2 * k < maxr_rep; k += Q) {
+                launch_full_unit(td, nt, nullptr, T.K.B.off.p, dtk.p, (int)k, 1.0, xin.p, st);
+                launch_prec_apply<double>(T.P, T.P.d64.p, T.K.B.off.p, nt, nullptr, xin.p, zout.p, T.ws64.p,
+                                          T.ys64.p, T.tw64.p, st);
+                launch_full_gather(td, nt, nullptr, T.K.B.off.p, dtk.p, (int)k, zout.p, dtsoff.p, Sg.p, st);
+                launch_full_unit(td, nt, nullptr, T.K.B.off.p, dtk.p, (int)k, 0.0, xin.p, st);
+            }
+            THM_HIP(hipStreamSynchronize(st));
         }
-        launch_invert_blocked(jobs, status.p, st);
+        // M = I + i C_G S_G in real form, inverted by Gauss-Jordan, then stored complex.  The
+        // representatives are inverted in batches of at most INV_BATCH_ELEMS matrix entries
+        // (three buffers of that size), so large boundary sets do not need all of them at once.
+        std::vector<int> reps;
+        for (int s = 0; s < ns; ++s)
+            if (isrep[s]) reps.push_back(s);
+        constexpr int64_t INV_BATCH_ELEMS = int64_t(1) << 30;  // 8 GiB per buffer
+        DBuf<int32_t> status(1);
+        THM_HIP(hipMemsetAsync(status.p, 0, sizeof(int32_t), st));
+        for (size_t q0 = 0; q0 < reps.size();) {
+            size_t q1 = q0;
+            int64_t btot = 0;
+            while (q1 < reps.size()) {
+                const int64_t e = 4 * full.r[reps[q1]] * full.r[reps[q1]];
+                if (q1 > q0 && btot + e > INV_BATCH_ELEMS) break;
+                btot += e;
+                ++q1;
+            }
+            DBuf<double> Bm(btot), Inv(btot), Wk(btot);
+            DBuf<int32_t> piv(std::max<int64_t>(4 * maxr_rep * (int64_t)(q1 - q0), 1));
+            std::vector<InvDesc> jobs;
+            int64_t bo = 0;
+            for (size_t q = q0; q < q1; ++q) {
+                const int s = reps[q];
+                const int r = (int)full.r[s];
+                launch_full_block(r, Sg.p + soff[s], full.cptr.p + goff[s], full.ccol.p, full.cval64.p, Bm.p + bo,
+                                  st);
+                jobs.push_back(
+                    {2 * r, Bm.p + bo, Wk.p + bo, Inv.p + bo, piv.p + 4 * maxr_rep * (int64_t)(q - q0), 2 * r});
+                bo += 4 * (int64_t)r * r;
+            }
+            launch_invert_blocked(jobs, status.p, st);
+            bo = 0;
+            for (size_t q = q0; q < q1; ++q) {
+                const int s = reps[q];
+                const int r = (int)full.r[s];
+                launch_full_extract(r, Inv.p + bo, full.m64.p + 2 * moff[s], full.m32.p + 2 * moff[s], st);
+                bo += 4 * (int64_t)r * r;
+            }
+            THM_HIP(hipStreamSynchronize(st));
+            if (std::getenv("THM_PROGRESS"))
+                std::fprintf(stderr, "[thm] complete inverse: inverted %zu of %zu boundary matrices, %.1f s\n", q1,
+                             reps.size(), (now_ms() - t0) * 1e-3);
+            q0 = q1;
+        }
         int32_t hs = 0;
         THM_HIP(hipMemcpyAsync(&hs, status.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         THM_HIP(hipStreamSynchronize(st));
         if (hs) fail(THM_ESINGULAR, "I + i C_G S_G is singular");
-        bo = 0;
-        for (int s : reps) {
-            const int r = (int)full.r[s];
-            launch_full_extract(r, Inv.p + bo, full.m64.p + 2 * moff[s], full.m32.p + 2 * moff[s], st);
-            bo += 4 * (int64_t)r * r;
-        }
-        THM_HIP(hipStreamSynchronize(st));
     }
     const int64_t gt = std::max<int64_t>(goff[ns], 1);
     full.u64.alloc(2 * gt);
@@ -763,15 +866,7 @@ KOps<float> Ctx::ops32(float csign, bool with_prec, int pkind) {
     };
     if (with_prec && pkind == 1) build_full();
     o.prec = [this, csign, pkind](const float *x, float *y, const int32_t *mask) {
-        if (!ws32.n) fail(THM_EINVAL, "preconditioner used before it was built");
-        launch_prec_apply<float>(P, P.d32.p, K.B.off.p, ns, mask, x, y, ws32.p, ys32.p, tw32.p, st);
-        if (pkind == 1) {
-            launch_full_correct<float>(full.d, ns, mask, K.B.off.p, csign < 0 ? 1 : 0, y, full.u32.p,
-                                       full.part32.p, full.w32.p, st);
-            launch_prec_apply<float>(P, P.d32.p, K.B.off.p, ns, mask, full.w32.p, full.y32.p, ws32.p, ys32.p,
-                                     tw32.p, st);
-            launch_axpy<float, float>(K.B, mask, full.neg1.p, full.y32.p, y, st);
-        }
+        prec32(pkind, csign, x, y, mask);
     };
     o.graphable = true;
     o.owner = this;
@@ -780,8 +875,21 @@ KOps<float> Ctx::ops32(float csign, bool with_prec, int pkind) {
     return o;
 }
 
-KOps<double> Ctx::ops_mixed(float csign) {
-    ops32(csign, true, 0);  // FP32 factor and work vectors
+void Ctx::prec32(int pkind, float csign, const float *x, float *y, const int32_t *mask) {
+    if (!ws32.n) fail(THM_EINVAL, "preconditioner used before it was built");
+    launch_prec_apply<float>(P, P.d32.p, K.B.off.p, ns, mask, x, y, ws32.p, ys32.p, tw32.p, st);
+    if (pkind == 1) {
+        // y -= K^{-1} P^T M^{-1} (+-i C_G y_G)
+        launch_full_correct<float>(full.d, ns, mask, K.B.off.p, csign < 0 ? 1 : 0, y, full.u32.p, full.part32.p,
+                                   full.w32.p, st);
+        launch_prec_apply<float>(P, P.d32.p, K.B.off.p, ns, mask, full.w32.p, full.y32.p, ws32.p, ys32.p, tw32.p,
+                                 st);
+        launch_axpy<float, float>(K.B, mask, full.neg1.p, full.y32.p, y, st);
+    }
+}
+
+KOps<double> Ctx::ops_mixed(float csign, int pk) {
+    ops32(csign, true, pk);  // FP32 factor and work vectors (and the FP32 boundary correction)
     if (!mx32.n) {
         mx32.alloc(K.B.Ltot);
         my32.alloc(K.B.Ltot);
@@ -792,15 +900,15 @@ KOps<double> Ctx::ops_mixed(float csign) {
     o.apply = [this, csign](const double *x, double *y, const double *b, const int32_t *mask) {
         spmv<double>(lpr64, mask, x, y, b, csign);
     };
-    o.prec = [this](const double *x, double *y, const int32_t *mask) {
+    o.prec = [this, csign, pk](const double *x, double *y, const int32_t *mask) {
         launch_scale<double, float>(K.B, mask, nullptr, 0, x, mx32.p, nullptr, 0, nullptr, st);
-        launch_prec_apply<float>(P, P.d32.p, K.B.off.p, ns, mask, mx32.p, my32.p, ws32.p, ys32.p, tw32.p, st);
+        prec32(pk, csign, mx32.p, my32.p, mask);
         launch_scale<float, double>(K.B, mask, nullptr, 0, my32.p, y, nullptr, 0, nullptr, st);
     };
     o.graphable = true;
     o.owner = this;
     o.csign = csign;
-    o.pkind = 2;
+    o.pkind = 2 + pk;
     return o;
 }
 
@@ -855,8 +963,9 @@ void Ctx::solve(const thm_solve_opts &o, float csign, const int32_t *mask, std::
     };
     if (!ir_aux.n) ir_aux.alloc(ns);
     if (!ir_scal.n) ir_scal.alloc(ns);
-    const bool classic = o.ir_mode != THM_IR_GMRES || pk != 0;
-    if (ir_sticky.size() != (size_t)ns) ir_sticky.assign(ns, 0);
+    const bool classic = o.ir_mode != THM_IR_GMRES;
+    std::vector<int32_t> &sticky = ir_sticky[pk];
+    if (sticky.size() != (size_t)ns) sticky.assign(ns, 0);
     {
         // GMRES-IR from the start for every system (THM_IR_GMRES) or for the systems whose
         // classical step has already failed to contract in this context
@@ -865,7 +974,7 @@ void Ctx::solve(const thm_solve_opts &o, float csign, const int32_t *mask, std::
         THM_HIP(hipStreamSynchronize(st));
         bool any_sticky = false;
         for (int i = 0; i < ns; ++i) {
-            fb[i] = hm[i] && (!classic || (pk == 0 && ir_sticky[i]));
+            fb[i] = hm[i] && (!classic || sticky[i]);
             any_sticky = any_sticky || fb[i];
             if (fb[i]) hm[i] = 0;
         }
@@ -885,7 +994,7 @@ void Ctx::solve(const thm_solve_opts &o, float csign, const int32_t *mask, std::
             if (undo[i]) {
                 any_undo = true;
                 fb[i] = 1;
-                if (pk == 0) ir_sticky[i] = 1;
+                sticky[i] = 1;
                 hi[i] = 0;
                 hr[i] = prev[i];
             }
@@ -935,7 +1044,7 @@ void Ctx::solve(const thm_solve_opts &o, float csign, const int32_t *mask, std::
     }
     bool any_fb = false;
     for (int i = 0; i < ns; ++i) any_fb = any_fb || fb[i];
-    if (any_fb && pk == 0) {
+    if (any_fb) {
         // GMRES-based refinement (Carson & Higham, SIAM J. Sci. Comput. 40 (2018)): where a
         // classical step with an FP32 inner solve did not contract, the correction is solved by
         // GMRES in FP64 (FP64 operator, basis, Hessenberg) with the FP32 factor as the
@@ -944,7 +1053,7 @@ void Ctx::solve(const thm_solve_opts &o, float csign, const int32_t *mask, std::
         // time, and a cycle must at least halve a system's FP64 residual (the same rule as a
         // classical step); a system that stalls (its FP32 factor too far from K^{-1}, e.g. near
         // a resonance) is finished with the FP64 factor below.
-        KOps<double> AM = ops_mixed(csign);
+        KOps<double> AM = ops_mixed(csign, pk);
         GmresParams cp = gp;
         cp.max_iter = K.m;
         std::vector<int32_t> in_ir(fb);

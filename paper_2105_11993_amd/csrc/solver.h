@@ -102,8 +102,11 @@ struct Krylov {
     DBuf<double> V64, w64, z64, cur64;
     DBuf<float> V32, w32, z32, cur32;
     static constexpr int NEV = 8;
+    // Arnoldi steps per captured graph: the host launches a cycle as chunks of this many steps
+    static constexpr int GRAPH_SPC = 8;
     int32_t *pinned = nullptr;  // NEV x ns host flags (coherent host memory, written by kernels)
     int32_t *pinned_dev = nullptr;  // the same memory as seen by kernels
+    int32_t *pinned_run = nullptr, *pinned_run_dev = nullptr;  // ns running flags of the current cycle
     DBuf<int32_t> step_ctr;     // Arnoldi steps of the current cycle (selects the flag slot)
     hipEvent_t ev[NEV] = {};
     struct GraphSlot {
@@ -113,7 +116,8 @@ struct Krylov {
         float csign = 0.f;
         double rtol = -1.0;
         const void *owner = nullptr;
-    } slots[6];
+        const void *b = nullptr, *x = nullptr;  // vectors baked into a cycle-turn graph
+    } slots[8][2];  // [precision, sign, preconditioner kind][chunk of steps, cycle turn]
     void init(const std::vector<int64_t> &n, int m, hipStream_t st);
     template <class T> T *V();
     template <class T> T *w();
@@ -133,8 +137,8 @@ struct KOps {
     bool graphable = false;
     const void *owner = nullptr;  // identity of the operator (graph cache key)
     float csign = 1.f;
-    int pkind = 0;                // preconditioner: 0 block diag(K, K)^{-1}, 1 complete (K +- iC)^{-1},
-                                  // 2 block diag(K, K)^{-1} with the FP32 factor inside FP64 GMRES (GMRES-IR)
+    int pkind = 0;                // preconditioner: 0 block diag(K, K)^{-1}, 1 complete (K +- iC)^{-1};
+                                  // 2, 3: the same two applied in FP32 inside FP64 GMRES (GMRES-IR)
 };
 
 struct GmresParams {
@@ -168,7 +172,7 @@ struct Ctx {
     DBuf<float> mx32, my32;        // FP32 copies of the GMRES-IR preconditioner's input and output
     // per system: a classical refinement step failed to contract in this context, so its later
     // THM_FP32_IR solves go straight to GMRES-IR (the context is rebuilt when K changes)
-    std::vector<int32_t> ir_sticky;
+    std::vector<int32_t> ir_sticky[2];  // per preconditioner kind (block, complete inverse)
     DBuf<double> rnorm, bnorm64, resid64;
     int lpr64 = 81, lpr32 = 81;  // SpMV variants (10 * lanes_per_row + unroll, or a SELL code)
     // groups of systems with the same K for the grouped SELL product (SPMV_SELL_GROUP)
@@ -199,7 +203,9 @@ struct Ctx {
     } full;
     void build_full();
 
-    void build(const std::vector<thm_system *> &s, int m, hipStream_t stream);
+    // spmv_setup: form the SpMV groups and run the SpMV autotuner (not needed by a context
+    // that only applies the preconditioner)
+    void build(const std::vector<thm_system *> &s, int m, hipStream_t stream, bool spmv_setup = true);
     void build_prec();
     // operator (and, unless with_prec is false, preconditioner) of the batch; pkind selects
     // the block preconditioner (0) or the complete inverse (1)
@@ -207,7 +213,10 @@ struct Ctx {
     KOps<float> ops32(float csign, bool with_prec = true, int pkind = 0);
     // FP64 operator with the block preconditioner applied by the FP32 factor (input rounded to
     // FP32, output widened): the correction solve of GMRES-based iterative refinement
-    KOps<double> ops_mixed(float csign);
+    KOps<double> ops_mixed(float csign, int pk = 0);
+    // y = P^{-1} x with the FP32 factor: block diag(K, K)^{-1} (pkind 0) or the complete
+    // inverse (pkind 1, transpose sign csign < 0)
+    void prec32(int pkind, float csign, const float *x, float *y, const int32_t *mask);
     // Solve A x = b for the systems in mask (device, nullable = all); b64/x64 slots hold
     // the right-hand sides and initial guesses (zero on Dirichlet rows).
     void solve(const thm_solve_opts &o, float csign, const int32_t *mask, std::vector<int> &iters,

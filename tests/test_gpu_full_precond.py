@@ -118,6 +118,11 @@ def test_gmres_with_full_preconditioner(thm, d):
                                                                precision=thm.THM_FP32_IR))
     assert st3["status"] == 0, st3
     assert rel(E3.cpu().numpy(), Eo) <= 1e-8
+    # GMRES-based refinement with the FP32 complete inverse as the preconditioner of FP64 GMRES
+    (E4,), (st4,) = thm.thm_gmres_solve([S], thm.default_opts(rtol=1e-12, precond=thm.THM_PREC_FULL,
+                                                               precision=thm.THM_FP32_IR, ir_mode=thm.THM_IR_GMRES))
+    assert st4["status"] == 0 and st4["gmres_ir"] == 1 and st4["fp64_fallback"] == 0, st4
+    assert rel(E4.cpu().numpy(), Eo) <= 1e-10
     # the block preconditioner needs many more steps on the same system
     (_,), (stb,) = thm.thm_gmres_solve([S], thm.default_opts(rtol=1e-12))
     assert stb["iters"] > st["iters"]
