@@ -168,75 +168,6 @@ void launch_dir_identity(int64_t n_skel, const int32_t *skel_dof, const uint8_t 
     THM_HIP(hipGetLastError());
 }
 
-// ------------------------------------------------------------------ batched FP64 GEMM (setup)
-// 64x64 tiles, 16-deep K steps staged through LDS, 4x4 outputs per thread.
-__global__ void __launch_bounds__(256) k_gemm(const GemmDesc *__restrict__ ds, const int32_t *__restrict__ blkoff,
-                                              int nd) {
-    __shared__ double As[16][65];
-    __shared__ double Bs[16][65];
-    const int di = find_sys2(blkoff, nd, blockIdx.x);
-    const GemmDesc d = ds[di];
-    const int tiles_n = (d.n + 63) / 64;
-    const int tile = blockIdx.x - blkoff[di];
-    const int tm = tile / tiles_n, tn = tile % tiles_n;
-    const int row0 = tm * 64, col0 = tn * 64;
-    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-    double acc[4][4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-    for (int k0 = 0; k0 < d.k; k0 += 16) {
-        for (int e = threadIdx.x; e < 1024; e += 256) {
-            const int r = e / 16, kk = e % 16;  // A tile: 64 rows x 16 k
-            const int gi = row0 + r, gk = k0 + kk;
-            double v = 0.0;
-            if (gi < d.m && gk < d.k) v = d.ta ? d.A[(int64_t)gk * d.lda + gi] : d.A[(int64_t)gi * d.lda + gk];
-            As[kk][r] = v;
-            const int kb = e / 64, cb = e % 64;  // B tile: 16 k x 64 cols
-            const int gk2 = k0 + kb, gj = col0 + cb;
-            double w = 0.0;
-            if (gk2 < d.k && gj < d.n) w = d.tb ? d.B[(int64_t)gj * d.ldb + gk2] : d.B[(int64_t)gk2 * d.ldb + gj];
-            Bs[kb][cb] = w;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < 16; ++kk) {
-            double a[4], b[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) { a[q] = As[kk][ty * 4 + q]; b[q] = Bs[kk][tx * 4 + q]; }
-#pragma unroll
-            for (int p = 0; p < 4; ++p)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) acc[p][q] = fma(a[p], b[q], acc[p][q]);
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int p = 0; p < 4; ++p) {
-        const int gi = row0 + ty * 4 + p;
-        if (gi >= d.m) continue;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int gj = col0 + tx * 4 + q;
-            if (gj >= d.n) continue;
-            double *cp = d.C + (int64_t)gi * d.ldc + gj;
-            *cp = d.alpha * acc[p][q] + (d.beta != 0.0 ? d.beta * *cp : 0.0);
-        }
-    }
-}
-
-void launch_gemm_batched(const std::vector<GemmDesc> &g, hipStream_t st, DBuf<GemmDesc> &scratch, Sched &sched) {
-    if (g.empty()) return;
-    std::vector<int64_t> tiles(g.size());
-    for (size_t i = 0; i < g.size(); ++i) tiles[i] = (int64_t)((g[i].m + 63) / 64) * ((g[i].n + 63) / 64);
-    sched.build(tiles, 1, st);
-    scratch.upload(g, st);
-    if (sched.nblocks == 0) return;
-    k_gemm<<<sched.nblocks, 256, 0, st>>>(scratch.p, sched.blkoff.p, (int)g.size());
-    THM_HIP(hipGetLastError());
-}
-
 __global__ void k_transpose(const double *A, int m, int n, int lda, double *At, int ldt, double alpha) {
     __shared__ double t[32][33];
     const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
@@ -371,6 +302,84 @@ template <> struct Mfma<double> {
     }
     static __device__ __forceinline__ int row(int g, int v) { return g + 4 * v; }
 };
+
+// ------------------------------------------------------------------ batched FP64 GEMM (setup)
+// C = alpha op(A) op(B) + beta C for a batch of matrices: 64 x 64 tiles of C per block, 16-deep
+// K steps staged through LDS, each wave a 32 x 32 quarter of the tile as 2 x 2 MFMA tiles
+// (v_mfma_f64_16x16x4f64: lane i + 16 g feeds A[i][k0 + g] and B[k0 + g][i]).  The order of
+// the sum over k is fixed, so results are reproducible.
+__global__ void __launch_bounds__(256) k_gemm(const GemmDesc *__restrict__ ds, const int32_t *__restrict__ blkoff,
+                                              int nd) {
+    using V4 = Mfma<double>::v4;
+    __shared__ double As[16][64 + 1];
+    __shared__ double Bs[16][64 + 1];
+    const int di = find_sys2(blkoff, nd, blockIdx.x);
+    const GemmDesc d = ds[di];
+    const int tiles_n = (d.n + 63) / 64;
+    const int tile = blockIdx.x - blkoff[di];
+    const int tm = tile / tiles_n, tn = tile % tiles_n;
+    const int row0 = tm * 64, col0 = tn * 64;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i16 = lane & 15, g = lane >> 4;
+    const int wr = 32 * (wave >> 1), wc = 32 * (wave & 1);
+    V4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = V4{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < d.k; k0 += 16) {
+        for (int e = threadIdx.x; e < 1024; e += 256) {
+            const int r = e / 16, kk = e % 16;  // A tile: 64 rows x 16 k
+            const int gi = row0 + r, gk = k0 + kk;
+            double v = 0.0;
+            if (gi < d.m && gk < d.k) v = d.ta ? d.A[(int64_t)gk * d.lda + gi] : d.A[(int64_t)gi * d.lda + gk];
+            As[kk][r] = v;
+            const int kb = e / 64, cb = e % 64;  // B tile: 16 k x 64 cols
+            const int gk2 = k0 + kb, gj = col0 + cb;
+            double w = 0.0;
+            if (gk2 < d.k && gj < d.n) w = d.tb ? d.B[(int64_t)gj * d.ldb + gk2] : d.B[(int64_t)gk2 * d.ldb + gj];
+            Bs[kb][cb] = w;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k4 = 0; k4 < 16; k4 += 4) {
+            double a[2], b[2];
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                a[t] = As[k4 + g][wr + 16 * t + i16];
+                b[t] = Bs[k4 + g][wc + 16 * t + i16];
+            }
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt) acc[mt][nt] = Mfma<double>::op(a[mt], b[nt], acc[mt][nt]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int gi = row0 + wr + 16 * mt + Mfma<double>::row(g, v);
+                const int gj = col0 + wc + 16 * nt + i16;
+                if (gi >= d.m || gj >= d.n) continue;
+                double *cp = d.C + (int64_t)gi * d.ldc + gj;
+                *cp = d.alpha * acc[mt][nt][v] + (d.beta != 0.0 ? d.beta * *cp : 0.0);
+            }
+}
+
+void launch_gemm_batched(const std::vector<GemmDesc> &g, hipStream_t st, DBuf<GemmDesc> &scratch, Sched &sched) {
+    if (g.empty()) return;
+    std::vector<int64_t> tiles(g.size());
+    for (size_t i = 0; i < g.size(); ++i) tiles[i] = (int64_t)((g[i].m + 63) / 64) * ((g[i].n + 63) / 64);
+    sched.build(tiles, 1, st);
+    scratch.upload(g, st);
+    if (sched.nblocks == 0) return;
+    k_gemm<<<sched.nblocks, 256, 0, st>>>(scratch.p, sched.blkoff.p, (int)g.size());
+    THM_HIP(hipGetLastError());
+}
 
 // Values per 16-byte piece, and the step column that value j of lane group g carries.
 static_assert(BCR_RT == 32 && BCR_KS == 32, "the lane order of a tile assumes 32 x 32 tiles");

@@ -64,6 +64,14 @@ template <> double *Krylov::z<double>() { return z64.p; }
 template <> float *Krylov::z<float>() { return z32.p; }
 template <> double *Krylov::cur<double>() { return cur64.p; }
 template <> float *Krylov::cur<float>() { return cur32.p; }
+template <> double *Krylov::Z<double>() { return Z64.p; }
+template <> float *Krylov::Z<float>() { return Z32.p; }
+template <> void Krylov::ensure_z<double>() {
+    if (!Z64.n) Z64.alloc((size_t)m * B.Ltot);
+}
+template <> void Krylov::ensure_z<float>() {
+    if (!Z32.n) Z32.alloc((size_t)m * B.Ltot);
+}
 
 template <>
 void Krylov::ensure<double>(hipStream_t) {
@@ -103,6 +111,15 @@ template <class T> struct TypeKey;
 template <> struct TypeKey<double> { static constexpr int v = 0; };
 template <> struct TypeKey<float> { static constexpr int v = 1; };
 
+// The complete inverse (pkind 1, 3) costs a step's worth of work per application and its
+// solves take a step or two: GMRES keeps Z = P^{-1} V and ends a cycle with x += Z y instead of
+// applying the preconditioner once more (flexible form; the same iterates for a fixed
+// preconditioner).
+template <class T>
+static bool flexible(const KOps<T> &ops) {
+    return ops.pkind == 1 || ops.pkind == 3;
+}
+
 template <class T>
 static void arnoldi_step(Krylov &K, const KOps<T> &ops, const GmresParams &p, int spc, hipStream_t st) {
     Batch &B = K.B;
@@ -110,6 +127,7 @@ static void arnoldi_step(Krylov &K, const KOps<T> &ops, const GmresParams &p, in
     T *V = K.V<T>(), *w = K.w<T>(), *z = K.z<T>(), *cur = K.cur<T>();
     int32_t *act = K.active.p;
     ops.prec(cur, z, act);
+    if (flexible(ops)) launch_scale<T, T>(B, act, nullptr, 0, z, K.Z<T>(), K.jcnt.p, B.Ltot, nullptr, st);
     ops.apply(z, w, nullptr, act);
     const int ldh = 2 * (m + 1);
     launch_dots<T>(B, act, K.jcnt.p, V, B.Ltot, w, K.part.p, p.cplx, st);
@@ -147,6 +165,11 @@ static void cycle_close(Krylov &K, const KOps<T> &ops, T *x, hipStream_t st) {
     Batch &B = K.B;
     T *V = K.V<T>(), *z = K.z<T>(), *cur = K.cur<T>();
     launch_hsolve(B, K.running.p, K.jcnt.p, K.H.p, K.g.p, K.y.p, K.m, st);
+    if (flexible(ops)) {
+        launch_lincomb<T>(B, K.running.p, K.jcnt.p, K.Z<T>(), B.Ltot, K.y.p, 2 * (K.m + 1), cur, st);
+        launch_axpy<T, T>(B, K.running.p, nullptr, cur, x, st);
+        return;
+    }
     launch_lincomb<T>(B, K.running.p, K.jcnt.p, V, B.Ltot, K.y.p, 2 * (K.m + 1), cur, st);
     ops.prec(cur, z, K.running.p);
     launch_axpy<T, T>(B, K.running.p, nullptr, z, x, st);
@@ -207,6 +230,7 @@ void gmres_run(Krylov &K, const KOps<T> &ops, const T *b, T *x, const int32_t *m
     Batch &B = K.B;
     const int ns = B.ns, m = K.m;
     K.ensure<T>(st);
+    if (flexible(ops)) K.ensure_z<T>();
     launch_norm2<T>(B, mask_in, b, K.part.p, st);
     launch_norm_finish(B, K.part.p, mask_in, K.bnorm.p, nullptr, 0.0, nullptr, nullptr, st);
     THM_HIP(hipMemcpyAsync(K.running.p, mask_in, sizeof(int32_t) * ns, hipMemcpyDeviceToDevice, st));

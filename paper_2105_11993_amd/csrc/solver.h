@@ -101,6 +101,10 @@ struct Krylov {
     DBuf<int32_t> running, active, jcnt, iters;
     DBuf<double> V64, w64, z64, cur64;
     DBuf<float> V32, w32, z32, cur32;
+    // preconditioned basis Z = P^{-1} V (m columns), kept when the preconditioner is costly
+    // relative to the step count (flexible form: x += Z y at the end of a cycle)
+    DBuf<double> Z64;
+    DBuf<float> Z32;
     static constexpr int NEV = 8;
     // Arnoldi steps per captured graph: the host launches a cycle as chunks of this many steps
     static constexpr int GRAPH_SPC = 8;
@@ -123,7 +127,9 @@ struct Krylov {
     template <class T> T *w();
     template <class T> T *z();
     template <class T> T *cur();
+    template <class T> T *Z();
     template <class T> void ensure(hipStream_t st);
+    template <class T> void ensure_z();
     void drop_graphs();
     ~Krylov();
 };
