@@ -2,16 +2,21 @@
 
 Paper Sec. 3.1, eqs. (5)-(10).  Omega is split into a box grid of
 non-overlapping subdomains Omega_i (eq. (5)); ids are 0-based, lexicographic with
-x fastest.  Each subdomain solves eq. (7) with the transmission operator S = 1
-(eq. (10)).  Readings used here (the printed indices of eqs. (6)-(8) are not
-consistent with each other):
+x fastest.  Each subdomain solves eq. (7) with the transmission operator S = s 1,
+a complex multiple of the identity (the paper's choice, eq. (10), is s = 1; the
+problem's `transmission` field gives s).  Readings used here (the printed indices
+of eqs. (6)-(8) are not consistent with each other):
  * subdomain i uses the data g_{j->i} coming from its neighbour j; its discrete
-   matrix is S_i = K_i + i k w (M_inf,i + sum_j M_Sigma_ij) (the transmission
-   coefficient is k w, as on Gamma^inf, without mu);
+   matrix is S_i = K_i + i k w (M_inf,i + s sum_j M_Sigma_ij) (the transmission
+   coefficient is k w, as on Gamma^inf, without mu); for complex s the term
+   i k w s M_Sigma has the real part -k w Im(s) M_Sigma, which joins K_i;
  * data are dual vectors on the DoFs of the closure of Sigma_ij that are not
    Dirichlet: G_{j->i}[v] = int_Sigma g_{j->i} . g^T phi_v; they enter the
    right-hand side of subdomain i as -G_{j->i};
- * update (eq. (8), S = 1): G_{i->j} = -G_{j->i} - 2 i k w M_Sigma_ij E_i;
+ * update (eq. (8)): G_{i->j} = -G_{j->i} - 2 i k w s M_Sigma_ij E_i; for any s != 0
+   the fixed point is still the global solution (G_ij + G_ji = -2 i k w s M_Sigma E_i
+   = -2 i k w s M_Sigma E_j forces continuity, and the summed subdomain rows lose their
+   interface terms);
  * the initial solves use G = 0 (homogeneous impedance on interfaces);
  * eq. (9): G^{k+1} = A0 G^k + b with A0 the linear part and b the update from
    the incident data alone; solved by Jacobi (the paper's iteration) or by
@@ -56,6 +61,9 @@ class DDM:
         nloc = [n[a] // S[a] for a in range(d)]
         self.subs = []
         nsub = int(np.prod(S))
+        self.s = complex(prob.transmission)
+        assert self.s != 0
+        kw = prob.kappa * prob.omega
         mu_g = prob.mu_cells(gm.n_cells).reshape(tuple(reversed(n)))
         eps_g = prob.eps_cells(gm.n_cells).reshape(tuple(reversed(n)))
         for s in range(nsub):
@@ -74,6 +82,17 @@ class DDM:
                          hi=tuple(hi) + (1.0,) * (3 - d), inc_faces=inc, mu=mu_l,
                          eps=eps_g[sl].ravel(), subdomains=(1, 1, 1))
             ls = system.assemble(lp)
+            if self.s != 1:
+                # interface sides carry k w s M_Sigma instead of the k w M_Sigma of an impedance side
+                Mi = None
+                for a in range(d):
+                    for side, inner in ((0, pos[a] > 0), (1, pos[a] < S[a] - 1)):
+                        if inner:
+                            m_ = system.side_matrix(ls.mesh, a, side)
+                            Mi = m_ if Mi is None else Mi + m_
+                if Mi is not None:
+                    ls.K = (ls.K - kw * self.s.imag * Mi).tocsr()
+                    ls.C = (ls.C + kw * (self.s.real - 1.0) * Mi).tocsr()
             # local -> global DoF map through the shared local cell ordering
             lm = ls.mesh
             l2g = np.full(lm.n_dofs, -1, dtype=np.int64)
@@ -168,11 +187,12 @@ class DDM:
         return Es
 
     def update(self, G, Es):
-        """Eq. (8) with S = 1 in dual form."""
+        """Eq. (8) with S = s 1 in dual form."""
         out = []
+        c = 2j * self.kw * self.s
         for f, (gab, gba) in zip(self.ifaces, G):
-            nab = -gba - 2j * self.kw * (f.Ma @ Es[f.a])
-            nba = -gab - 2j * self.kw * (f.Mb @ Es[f.b])
+            nab = -gba - c * (f.Ma @ Es[f.a])
+            nba = -gab - c * (f.Mb @ Es[f.b])
             out.append((nab, nba))
         return out
 

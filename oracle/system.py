@@ -45,6 +45,7 @@ class Problem:
     hi: tuple = (1.0, 1.0, 1.0)
     subdomains: tuple = (1, 1, 1)
     eps: np.ndarray = None           # relative permittivity per cell (refractive index squared); None -> 1
+    transmission: complex = 1.0      # DDM: transmission operator S = s 1 on interfaces (eq. (10): s = 1)
 
     def mesh(self):
         return BoxMesh(self.dim, self.n, self.lo, self.hi, self.p)

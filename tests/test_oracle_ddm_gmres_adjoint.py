@@ -59,6 +59,26 @@ def test_ddm_fixed_point_is_global_solution(dim, m, p, S):
     assert np.linalg.norm(E - Eg) <= 1e-9 * np.linalg.norm(Eg)
 
 
+@pytest.mark.parametrize("dim,m,p,S,ts", [(2, 8, 1, (2, 2, 1), 0.6 + 0.8j), (2, 8, 0, (2, 1, 1), 2.0),
+                                          (3, 4, 1, (2, 1, 1), 1.5 - 0.5j)])
+def test_ddm_fixed_point_with_scaled_transmission(dim, m, p, S, ts):
+    """S = s 1 on the interfaces (eq. (7)-(8) with a complex scalar s instead of the paper's 1):
+    the interface iteration changes -- its first Jacobi iterate differs from the s = 1 one --
+    but its fixed point is the same global discrete solution."""
+    th = 0.3
+    base = dict(dim=dim, n=(m,) * dim + (1,) * (3 - dim), p=p, omega=6.0,
+                mu=np.random.default_rng(2).uniform(1, 2, m ** dim),
+                inc_dir=(np.cos(th), np.sin(th), 0.0), inc_pol=(-np.sin(th), np.cos(th), 0.0), subdomains=S)
+    D = ddm.DDM(Problem(**base, transmission=ts))
+    E, it, _ = D.solve_gmres(rtol=1e-12)
+    Eg = system.solve_lu(D.glob)
+    assert np.linalg.norm(E - Eg) <= 1e-9 * np.linalg.norm(Eg)
+    D1 = ddm.DDM(Problem(**base))
+    J1, _ = D1.jacobi(2)
+    Js, _ = D.jacobi(2)
+    assert np.linalg.norm(J1[1] - Js[1]) > 1e-3 * np.linalg.norm(Eg)
+
+
 def test_ddm_single_subdomain_is_single_domain_solve():
     pr = Problem(**workloads.c1())
     D = ddm.DDM(pr)
