@@ -7,6 +7,11 @@ Workload (one step = one full solve of the hot path on resident inputs):
   outer GMRES on the interface system, subdomain solves by block-preconditioned
   GMRES, stop when the glued field's global FP64 relative residual <= 1e-8.
 
+The same line carries, untimed by the step loop: the other forms of that solve (batched
+FP64, plain FP64, the complete-inverse ablation), the block SpMV on the 1.03 GB operator of
+the 3D configuration, the 3D configuration at full size (32^3 hexes, 2x2x2 subdomains), the
+256-problem batch at full size, and the oracle's timed run on the host (cpu_baseline).
+
 Prints one JSON line.  Run with --gpus 1 (the default); one GPU only.
 """
 import argparse
@@ -29,15 +34,17 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["c2", "c3", "c4", "c5", "block"], default="c2",
+    ap.add_argument("--workload", choices=["c2", "c3", "c4", "c5", "block", "tsweep", "spmv"], default="c2",
                     help="c2 (default, the benchmark line; also carries the 256-problem batch and the >= 1 GB "
                          "SpMV); c3: 3D DDM; c4: batch of uneven independent problems alone; c5: adjoint "
-                         "gradient vs central differences; block: the block benchmark's w sweep")
+                         "gradient vs central differences; block: the block benchmark's w sweep; tsweep: outer steps for "
+                         "transmission operators S = s 1; spmv: the block SpMV on the 1.03 GB 3D operator alone")
     ap.add_argument("--mesh", type=int, default=None, help="cells per side (c2: 256, c3: 32, c5: 128, block: 128)")
     ap.add_argument("--count", type=int, default=256, help="c4: number of problems")
     ap.add_argument("--scale", type=int, default=1, help="c4 workload: divide every mesh size by this")
     ap.add_argument("--c4-scale", type=int, default=1, help="c2 line: mesh divisor of its 256-problem batch leg")
     ap.add_argument("--skip-c4", action="store_true", help="c2 line: leave out the 256-problem batch leg")
+    ap.add_argument("--skip-c3", action="store_true", help="c2 line: leave out the 3D 32^3 leg")
     ap.add_argument("--c4-restart", type=int, default=32,
                     help="GMRES restart of the 256-problem batch (32: at full size its factors take 243 GB of the "
                          "288 GB, so the Krylov basis is kept short)")
@@ -267,6 +274,21 @@ def c4_leg(args, thm, torch, workloads, scale, steps=1, warmup=1):
         ms, by = thm.thm_time_spmv_systems(systems, prec, reps=20)
         spmv[name] = {"ms": ms, "bytes": by, "GBps": by / ms / 1e6}
     log(args, f"c4 spmv over all problems: {spmv}")
+    full_rec = None
+    if not args.skip_full:
+        # ablation: the complete inverse (K + iC)^{-1} of each problem (Sec. 3.2's alternative,
+        # applied exactly), batched FP64; a solve takes one or two steps, so restart 4 (a context
+        # of its own, with a short basis)
+        of = thm.default_opts(precision=thm.THM_FP64, batched=1, use_graph=1, precond=thm.THM_PREC_FULL,
+                              **dict(common, restart=4))
+        t0 = time.perf_counter()
+        thm.thm_gmres_solve(systems, of, allow_not_converged=True)  # context, boundary inverses, graphs
+        torch.cuda.synchronize()
+        t_first = time.perf_counter() - t0
+        dt, (_, stf) = timed(lambda: thm.thm_gmres_solve(systems, of, allow_not_converged=True))
+        full_rec = dict(_batch_form(stf, dt), first_call_s=t_first,
+                        extra_bytes=max(s["precond_extra_bytes"] for s in stf))
+        log(args, f"c4 complete inverse fp64: {full_rec}")
     plain_rec = None
     if not args.skip_plain:
         # one problem at a time, each with its own workspace, freed after its solve (the batch's
@@ -288,6 +310,7 @@ def c4_leg(args, thm, torch, workloads, scale, steps=1, warmup=1):
            "problems": len(specs), "n_dofs_total": n_tot, "assembly_s": t_asm,
            "batched_fp32_refine": fast_rec, "batched_fp64": b64_rec, "plain_fp64": plain_rec,
            "speedup_vs_plain_fp64": (plain_rec["s"] / fast_rec["s"]) if plain_rec else None,
+           "full_inverse_ablation_fp64": full_rec,
            "spmv_all_problems": spmv,
            "factor_bytes": sum(s.fresh_info()["factor_bytes"] for s in systems)}
     for s in systems:
@@ -395,19 +418,18 @@ def spmv_c3_global(args, thm, torch, workloads):
     return out
 
 
-def run_c3(args, thm, torch, workloads):
+def c3_leg(args, thm, torch, workloads, block_outer=0):
     """The 3D configuration (unit cube, 32^3 hexes, degree 1, w = 20, mu ~ U[1,2] per cell, 2x2x2
     subdomains of 16^3) at full size.  Time to a global FP64 residual of 1e-8 of the DDM with the
     subdomain solves preconditioned by the complete inverse (K + iC)^{-1} of each subdomain system
     (Sec. 3.2's alternative, applied exactly: K^{-1} plus a boundary correction), batched, FP64 --
     and, if asked, GMRES-based refinement with its FP32 form.  The paper's block preconditioner
     diag(K, K)^{-1} (eq. (11)) needs hundreds of subdomain GMRES steps per outer step at this size;
-    its batched FP64 and GMRES-IR forms are run for a few outer steps only (--c3-block-outer) and
-    reported per outer step with the projection to the complete-inverse run's outer count.  The
-    headline residual of the fastest form's field is recomputed by the oracle's own operator (the
+    with block_outer > 0 its batched FP64 and GMRES-IR forms run for that many outer steps and are
+    reported per batched subdomain solve with the projection to the complete-inverse run's outer
+    count.  The residual of the timed field is recomputed by the oracle's own operator (the
     oracle's direct solvers exceed any bounded CPU time at 811,200 DoFs)."""
-    import numpy as np
-    m = args.mesh or 32
+    m = args.mesh if (args.mesh and args.workload == "c3") else 32
     d = workloads.c3(m)
     t0 = time.perf_counter()
     S = thm.thm_assemble(d)
@@ -436,8 +458,9 @@ def run_c3(args, thm, torch, workloads):
     torch.cuda.synchronize()
     t_first = time.perf_counter() - t0
     log(args, f"c3 complete inverse fp64, first call (setup included): {t_first:.1f}s {st0}")
+    steps = max(args.steps, 1) if args.workload == "c3" else 1
     runs = []
-    for k in range(max(args.steps, 1)):
+    for k in range(steps):
         rec, _ = timed(full64, "full_inverse_fp64")
         runs.append(rec)
         log(args, f"c3 step {k}: {rec}")
@@ -451,32 +474,34 @@ def run_c3(args, thm, torch, workloads):
         thm.thm_ddm_solve(S, dict_opts(thm, o, max_outer=1), allow_not_converged=True)
         forms["full_inverse_gmres_ir_fp32"], _ = timed(o, "full_inverse_gmres_ir_fp32")
         log(args, f"c3 complete inverse GMRES-IR: {forms['full_inverse_gmres_ir_fp32']}")
-    # the paper's block preconditioner: a few outer steps, per outer step
+    # the paper's block preconditioner: a few outer steps, per batched subdomain solve
     capped = {}
     for name, kw in (("block_fp64", dict(precision=thm.THM_FP64)),
                      ("block_gmres_ir_fp32", dict(precision=thm.THM_FP32_IR, ir_mode=thm.THM_IR_GMRES))):
-        if args.c3_block_outer <= 0:
+        if block_outer <= 0:
             break
-        o = thm.default_opts(**dict(common, max_outer=args.c3_block_outer, relax_inner=0), **kw)
+        o = thm.default_opts(**dict(common, max_outer=block_outer, relax_inner=0), **kw)
         rec, st = timed(o, name)
         # a DDM run is (outer steps + 2) batched subdomain solves: the right-hand side b = A(0),
         # one per outer step, and the final field
         nsolve = rec["outer_iters"] + 2
         per_solve = rec["s"] / nsolve
-        capped[name] = dict(rec, capped_at_outer=args.c3_block_outer, s_per_subdomain_batch=per_solve,
+        capped[name] = dict(rec, capped_at_outer=block_outer, s_per_subdomain_batch=per_solve,
                             inner_per_subdomain_batch=rec["inner_iters"] / nsolve,
                             projected_s=per_solve * (best["outer_iters"] + 2))
         log(args, f"c3 {name} (capped): {capped[name]}")
-    ms, by, nl = thm.thm_time_precond(S, thm.THM_FP64, reps=5)
+    ms, by, nl = thm.thm_time_precond(S, thm.THM_FP64, reps=3)
     roof = {"bound": "hbm", "kernel": "k_bcr_mfma<double,4> (batched FP64 cyclic-reduction MFMA products, 8 "
                                       "subdomains of 16^3; two per complete-inverse application)",
             "achieved": by / ms / 1e6, "peak": 8000.0, "unit": "GB/s", "frac": by / ms / 1e6 / 8000.0,
-            "traffic": None, "launches_per_apply": nl, "avg_launch_us": ms / nl * 1e3, "bytes_per_apply": by}
+            "launches_per_apply": nl, "avg_launch_us": ms / nl * 1e3, "bytes_per_apply": by}
     log(args, f"c3 roofline: {roof}")
-    fresh = S.fresh_info()
     Eh = fields["full_inverse_fp64"].cpu().numpy()
     S.close()
     del fields
+    import gc
+    gc.collect()
+    torch.cuda.empty_cache()
     oracle = None
     if not args.no_cpu_baseline:
         from oracle import system
@@ -491,18 +516,29 @@ def run_c3(args, thm, torch, workloads):
                                   "residual, at 16^3 and 8^3 on the GPU tests"}
         log(args, f"c3 oracle residual of the field: {oracle}")
     ok = best["converged"] and (oracle is None or oracle["oracle_rel_residual"] <= 1e-8)
+    return {"workload": f"3D unit cube, {m}^3 hexes, Nedelec degree 1, w=20, kappa=1, mu ~ U[1,2] per cell "
+                        f"(seed 3), plane wave on x=0, impedance elsewhere, 2x2x2 subdomains, "
+                        f"impedance-transmission DDM (interface GMRES), tol 1e-8",
+            "n_dofs": info["n_dofs"], "nnz": info["nnz"], "assembly_s": t_asm, "converged": ok,
+            "form": "batched subdomain solves preconditioned by the complete inverse (K + iC)^{-1}, FP64",
+            "time_to_1e-8_s": best["s"], "forms": forms, "block_preconditioner_capped": capped,
+            "roofline_fp64_bcr": roof, "oracle": oracle}
+
+
+def run_c3(args, thm, torch, workloads):
+    """The 3D configuration as the benchmark line (--workload c3)."""
+    rec = c3_leg(args, thm, torch, workloads, block_outer=args.c3_block_outer)
+    best = rec["forms"]["full_inverse_fp64"]
+    ok = rec["converged"]
     out = {
         "metric": "time-to-1e-8 residual & SpMV GB/s: batched/FP32+refine vs plain FP64",
         "value": best["s"] if ok else None, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
         "ms_per_step": best["s"] * 1e3 if ok else None, "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic", "converged": ok,
-        "config": {"workload": f"3D unit cube, {m}^3 hexes, Nedelec degree 1, w=20, kappa=1, mu ~ U[1,2] per cell "
-                               f"(seed 3), plane wave on x=0, impedance elsewhere, 2x2x2 subdomains, "
-                               f"impedance-transmission DDM (interface GMRES), tol 1e-8",
-                   "n_dofs": info["n_dofs"], "nnz": info["nnz"], "restart": args.restart,
-                   "form": "batched subdomain solves preconditioned by the complete inverse (K + iC)^{-1}, FP64"},
-        "assembly_s": t_asm, "forms": forms, "block_preconditioner_capped": capped,
-        "factor_bytes": fresh["factor_bytes"], "roofline": roof, "oracle": oracle,
+        "config": {"workload": rec["workload"], "n_dofs": rec["n_dofs"], "nnz": rec["nnz"], "restart": args.restart,
+                   "form": rec["form"]},
+        "roofline": dict(rec["roofline_fp64_bcr"], traffic=None),
+        **{k: v for k, v in rec.items() if k not in ("workload", "form", "roofline_fp64_bcr")},
     }
     print(json.dumps(out))
     if not ok:
@@ -517,6 +553,38 @@ def dict_opts(thm, o, **kw):
     for k, v in kw.items():
         setattr(c, k, v)
     return c
+
+
+TS_VALUES = [1.0, 0.5, 2.0, 1.0 + 0.5j, 1.0 - 0.5j, 0.7071067811865476 + 0.7071067811865476j,
+             0.7071067811865476 - 0.7071067811865476j]
+
+
+def run_transmission_sweep(args, thm, torch, workloads):
+    """The transmission operator S = s 1 of eqs. (7)-(8) for a few complex s (s = 1 is the paper's
+    eq. (10)) on the 2D benchmark geometry (--mesh, default 256^2, degree 2, w = 50, 4x4 subdomains):
+    outer interface-GMRES steps and time to a global residual of 1e-8, subdomain solves by the
+    complete inverse in FP64 (so the outer step count, which s changes, dominates).  One JSON line."""
+    m = args.mesh or 256
+    rows = []
+    for ts in TS_VALUES:
+        d = dict(workloads.c2(m), transmission=ts)
+        S = thm.thm_assemble(d)
+        o = thm.default_opts(rtol=1e-8, inner_rtol=args.inner_rtol, restart=args.restart, max_outer=args.max_outer,
+                             precision=thm.THM_FP64, precond=thm.THM_PREC_FULL, batched=1, use_graph=1)
+        thm.thm_ddm_solve(S, o, allow_not_converged=True)  # factors, boundary inverses, graphs
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = thm.thm_ddm_solve(S, o, allow_not_converged=True)
+        torch.cuda.synchronize()
+        row = {"s_re": float(complex(ts).real), "s_im": float(complex(ts).imag), "s": time.perf_counter() - t0,
+               "outer_iters": st["outer_iters"], "inner_iters": st["iters"], "rel_residual": st["rel_residual"],
+               "converged": bool(st["status"] == 0 and st["rel_residual"] <= 1e-8)}
+        log(args, f"transmission s={ts}: {row}")
+        rows.append(row)
+        S.close()
+    print(json.dumps({"workload": f"2D unit square, {m}x{m} quads, Nedelec degree 2, w=50, 4x4 subdomains, "
+                                  f"impedance-transmission DDM with S = s 1, interface GMRES to 1e-8, subdomain "
+                                  f"solves by the complete inverse (FP64)", "data": "synthetic", "sweep": rows}))
 
 
 def run_block_sweep(args, thm, torch, workloads):
@@ -574,6 +642,12 @@ def main():
         return
     if args.workload == "block":
         run_block_sweep(args, thm, torch, workloads)
+        return
+    if args.workload == "tsweep":
+        run_transmission_sweep(args, thm, torch, workloads)
+        return
+    if args.workload == "spmv":
+        print(json.dumps(dict(spmv_c3_global(args, thm, torch, workloads), data="synthetic")))
         return
     if args.workload == "c3" and not args.c3_block_timed:
         run_c3(args, thm, torch, workloads)
@@ -704,6 +778,10 @@ def main():
     if args.workload == "c2" and not args.skip_spmv_c3:
         spmv_big = spmv_c3_global(args, thm, torch, workloads)
         log(args, f"spmv (>= 1 GB operator): {spmv_big}")
+    c3 = None
+    if args.workload == "c2" and not args.skip_c3:
+        c3 = c3_leg(args, thm, torch, workloads)
+        log(args, f"c3 leg: {c3}")
     c4 = None
     if args.workload == "c2" and not args.skip_c4:
         c4 = c4_leg(args, thm, torch, workloads, args.c4_scale)
@@ -711,7 +789,7 @@ def main():
     copy = copy_bandwidth(torch)
     log(args, f"device copy: {copy}")
 
-    forms_ok = all(r is None or r["converged"] for r in (result_b64, result_plain))
+    forms_ok = all(r is None or r["converged"] for r in (result_b64, result_plain, c3))
     out = {
         "metric": "time-to-1e-8 residual & SpMV GB/s: batched/FP32+refine vs plain FP64",
         "value": t_fast if all_converged else None, "unit": "s", "n_gpus": 1, "steps": args.steps,
@@ -735,6 +813,7 @@ def main():
         "spmv": spmv,
         "spmv_batch": spmv_batch,
         "spmv_ge_1GB": spmv_big,
+        "c3_full_size": c3,
         "c4_batch": c4,
         "roofline": roof,
         "device_copy": copy,

@@ -95,6 +95,12 @@ typedef struct {
     const double *eps;       /* host, n_cells relative permittivities > 0 (x fastest): a material of
                                 refractive index n (Sec. 4.1's block benchmark) has eps = n^2 and enters
                                 the mass term, K_c = mu_c^{-1} A_c - w^2 eps_c M_c; NULL -> 1 (eq. (3)) */
+    double transmission[2];  /* DDM transmission operator S = s 1 on the interfaces, s = transmission[0]
+                                + i transmission[1] (eqs. (7)-(8): subdomain i carries i k w s M_Sigma on
+                                its interfaces, the update is G_{i->j} = -G_{j->i} - 2 i k w s M_Sigma E_i);
+                                the paper's S = 1 (eq. (10)) is {1, 0}, and {0, 0} also means s = 1.  Any
+                                s != 0 keeps the global discrete solution as the fixed point; Re(s) > 0 keeps
+                                the subdomain problems absorbing.  Ignored without a partition. */
 } thm_problem;
 
 /* Solver options.  thm_default_opts fills the defaults listed here. */

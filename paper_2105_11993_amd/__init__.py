@@ -33,7 +33,7 @@ class ThmProblem(ctypes.Structure):
                 ("degree", ctypes.c_int32), ("omega", ctypes.c_double), ("kappa", ctypes.c_double),
                 ("mu", ctypes.POINTER(ctypes.c_double)), ("inc_faces", ctypes.c_uint32), ("inc_dir", _d3),
                 ("inc_pol_re", _d3), ("inc_pol_im", _d3), ("subdomains", _i3),
-                ("eps", ctypes.POINTER(ctypes.c_double))]
+                ("eps", ctypes.POINTER(ctypes.c_double)), ("transmission", ctypes.c_double * 2)]
 
 
 class ThmSolveOpts(ctypes.Structure):
@@ -149,7 +149,7 @@ def default_opts(**kw):
 
 def make_problem(d):
     """ThmProblem from a workload dict (dim, n, p, omega, kappa, mu, inc_faces, inc_dir,
-    inc_pol, lo, hi, subdomains, eps).  Returns (struct, keep-alive buffers)."""
+    inc_pol, lo, hi, subdomains, eps, transmission).  Returns (struct, keep-alive buffers)."""
     p = ThmProblem()
     dim = int(d["dim"])
     p.dim = dim
@@ -177,6 +177,8 @@ def make_problem(d):
     p.inc_pol_im = _d3(*[v.imag for v in pol[:3]])
     sub = list(d.get("subdomains", (1, 1, 1))) + [1] * 3
     p.subdomains = _i3(*[int(v) for v in sub[:3]])
+    ts = complex(d.get("transmission", 1.0))
+    p.transmission = (ctypes.c_double * 2)(ts.real, ts.imag)
     return p, keep
 
 

@@ -329,6 +329,14 @@ void launch_gather(int64_t nnz, const int32_t *gptr, const int32_t *gsrc, const 
 void launch_side_mass(int dim, int nsides, const int32_t *side_axis, const int32_t *side_side,
                       const int32_t *side_fn, int nf, int n_loc, const FeTables *tabs_dev_host[6],
                       const double *h, double *out, hipStream_t st);
+// Interface sides of a DDM subdomain with a transmission factor s (see thm_problem.transmission):
+// scale the side blocks selected by the bit mask sel (bit 2 axis + side), and add a multiple of
+// side blocks [s0, s1) of one (axis, side) group into the element matrices of their cells.
+void launch_side_scale(int nsides, const int32_t *side_axis, const int32_t *side_side, uint32_t sel, int nf,
+                       double f, const double *in, double *out, hipStream_t st);
+void launch_side_to_elem(int s0, int s1, const int32_t *side_cell, const int32_t *side_axis,
+                         const int32_t *side_side, const int32_t *side_fn, int nf, int n_loc, double coef,
+                         const double *blk, double *kel, hipStream_t st);
 void launch_side_load(int dim, int nsides, const int32_t *side_cell, const int32_t *side_axis,
                       const int32_t *side_side, const int32_t *side_fn, int nf, int n_loc,
                       const FeTables *tabs[6], const double *h, const double *lo, const int32_t *ncell3,
@@ -354,9 +362,11 @@ void launch_sum(const double *x, int64_t n, double *out, hipStream_t st);
 // ---- domain decomposition and small helpers (kernels_ddm.hip)
 void launch_ddm_rhs(int64_t ntouch, const int32_t *touch_sys, const int32_t *touch_dof, const int32_t *touch_ptr,
                     const int32_t *touch_src, double *const *rhs, const double *G, hipStream_t st);
+// G update of eq. (8) with S = s 1 (s = s_re + i s_im): u_e = -G[rev(e)] - 2 i k w s (M_Sigma E)[e]
 void launch_ddm_update(int64_t nent, const int32_t *ent_sys, const int32_t *ent_row, const int32_t *ent_rev,
                        const int32_t *ent_mptr, const int32_t *m_col, const double *m_val,
-                       const double *const *X, const double *G, double kw, int mode, double *out, hipStream_t st);
+                       const double *const *X, const double *G, double kw, double s_re, double s_im, int mode,
+                       double *out, hipStream_t st);
 void launch_ddm_glue(int64_t n, const int32_t *own_sys, const int32_t *own_loc, const double *const *X, double *E,
                      hipStream_t st);
 void launch_diag_solve(int64_t n, const double *d, const double *r, double *z, hipStream_t st);

@@ -32,15 +32,15 @@ void launch_ddm_rhs(int64_t ntouch, const int32_t *touch_sys, const int32_t *tou
     THM_HIP(hipGetLastError());
 }
 
-// For every directed-interface entry e (sender s, local row la):
-//   u_e = -G[rev(e)] - 2 i k w (M_Sigma E_s)[la]
+// For every directed-interface entry e (sender s, local row la), transmission S = s 1:
+//   u_e = -G[rev(e)] - 2 i k w s (M_Sigma E_s)[la]
 //   mode 0: out_e = u_e          (Jacobi sweep / affine term b)
 //   mode 1: out_e = G_e - u_e    ((I - A0) G)
 __global__ void k_ddm_update(int64_t nent, const int32_t *__restrict__ ent_sys, const int32_t *__restrict__ ent_row,
                              const int32_t *__restrict__ ent_rev, const int32_t *__restrict__ ent_mptr,
                              const int32_t *__restrict__ m_col, const double *__restrict__ m_val,
-                             const double *const *__restrict__ X, const double *__restrict__ G, double kw, int mode,
-                             double *__restrict__ out) {
+                             const double *const *__restrict__ X, const double *__restrict__ G, double kw,
+                             double s_re, double s_im, int mode, double *__restrict__ out) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= nent) return;
     const double *Es = X[ent_sys[e]];
@@ -53,9 +53,10 @@ __global__ void k_ddm_update(int64_t nent, const int32_t *__restrict__ ent_sys, 
     }
     (void)ent_row;
     const int64_t r = ent_rev[e];
-    // -2 i kw (mr + i mi) = 2 kw mi - 2 i kw mr
-    const double ur = -G[2 * r] + 2.0 * kw * mi;
-    const double ui = -G[2 * r + 1] - 2.0 * kw * mr;
+    // t = s (mr + i mi);  -2 i kw t = 2 kw Im(t) - 2 i kw Re(t)
+    const double tr = s_re * mr - s_im * mi, ti = s_re * mi + s_im * mr;
+    const double ur = -G[2 * r] + 2.0 * kw * ti;
+    const double ui = -G[2 * r + 1] - 2.0 * kw * tr;
     if (mode == 0) {
         out[2 * e] = ur;
         out[2 * e + 1] = ui;
@@ -67,10 +68,11 @@ __global__ void k_ddm_update(int64_t nent, const int32_t *__restrict__ ent_sys, 
 
 void launch_ddm_update(int64_t nent, const int32_t *ent_sys, const int32_t *ent_row, const int32_t *ent_rev,
                        const int32_t *ent_mptr, const int32_t *m_col, const double *m_val,
-                       const double *const *X, const double *G, double kw, int mode, double *out, hipStream_t st) {
+                       const double *const *X, const double *G, double kw, double s_re, double s_im, int mode,
+                       double *out, hipStream_t st) {
     if (!nent) return;
     k_ddm_update<<<(unsigned)((nent + 255) / 256), 256, 0, st>>>(nent, ent_sys, ent_row, ent_rev, ent_mptr, m_col,
-                                                                 m_val, X, G, kw, mode, out);
+                                                                 m_val, X, G, kw, s_re, s_im, mode, out);
     THM_HIP(hipGetLastError());
 }
 

@@ -313,6 +313,51 @@ void launch_side_mass(int dim, int nsides, const int32_t *side_axis, const int32
     THM_HIP(hipGetLastError());
 }
 
+// out[si] = f in[si] for the side blocks (nf x nf each) whose (axis, side) bit 2 axis + side is
+// set in sel, out[si] = in[si] for the others.
+__global__ void k_side_scale(int nsides, const int32_t *__restrict__ side_axis, const int32_t *__restrict__ side_side,
+                             uint32_t sel, int nf, double f, const double *__restrict__ in, double *__restrict__ out) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (int64_t)nsides * nf * nf) return;
+    const int si = (int)(id / (nf * nf));
+    const bool on = (sel >> (2 * side_axis[si] + side_side[si])) & 1u;
+    out[id] = on ? f * in[id] : in[id];
+}
+
+void launch_side_scale(int nsides, const int32_t *side_axis, const int32_t *side_side, uint32_t sel, int nf,
+                       double f, const double *in, double *out, hipStream_t st) {
+    const int64_t tot = (int64_t)nsides * nf * nf;
+    if (!tot) return;
+    k_side_scale<<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(nsides, side_axis, side_side, sel, nf, f, in, out);
+    THM_HIP(hipGetLastError());
+}
+
+// kel[c][u_a][u_b] += coef blk[si][a][b] for the sides si in [s0, s1) of one (axis, side) group, c
+// the side's cell and u the side's local functions (a group holds each cell once, so the adds
+// of one launch do not collide and every entry is summed in launch order).
+__global__ void k_side_to_elem(int s0, int s1, const int32_t *__restrict__ side_cell,
+                               const int32_t *__restrict__ side_axis, const int32_t *__restrict__ side_side,
+                               const int32_t *__restrict__ side_fn, int nf, int n_loc, double coef,
+                               const double *__restrict__ blk, double *__restrict__ kel) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (int64_t)(s1 - s0) * nf * nf) return;
+    const int si = s0 + (int)(id / (nf * nf));
+    const int a = (int)((id / nf) % nf), b = (int)(id % nf);
+    const int stt = 2 * side_axis[si] + side_side[si];
+    const int ua = side_fn[stt * nf + a], ub = side_fn[stt * nf + b];
+    kel[((int64_t)side_cell[si] * n_loc + ua) * n_loc + ub] += coef * blk[(int64_t)si * nf * nf + a * nf + b];
+}
+
+void launch_side_to_elem(int s0, int s1, const int32_t *side_cell, const int32_t *side_axis,
+                         const int32_t *side_side, const int32_t *side_fn, int nf, int n_loc, double coef,
+                         const double *blk, double *kel, hipStream_t st) {
+    const int64_t tot = (int64_t)(s1 - s0) * nf * nf;
+    if (tot <= 0) return;
+    k_side_to_elem<<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(s0, s1, side_cell, side_axis, side_side, side_fn,
+                                                                  nf, n_loc, coef, blk, kel);
+    THM_HIP(hipGetLastError());
+}
+
 // s_a = int_side gamma^T(E^inc) . gamma^T(phi_a) ds with E^inc = pol exp(-i w d.x); complex output.
 __global__ void k_side_load(int dim, int nsides, const int32_t *side_cell, const int32_t *side_axis,
                             const int32_t *side_side, const int32_t *side_fn, int nf, int n_loc, int nps,

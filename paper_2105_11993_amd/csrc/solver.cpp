@@ -175,8 +175,15 @@ static void cycle_close(Krylov &K, const KOps<T> &ops, T *x, hipStream_t st) {
     launch_axpy<T, T>(B, K.running.p, nullptr, z, x, st);
 }
 
+// Arnoldi steps per chunk graph: GRAPH_SPC, or one step where a solve takes only a step or
+// two (the complete inverse), so that few steps run past convergence.
+template <class T>
+static int chunk_steps(const KOps<T> &ops) {
+    return flexible(ops) ? 1 : Krylov::GRAPH_SPC;
+}
+
 // Captured once per (precision, operator, options, kind, vectors) and replayed: kind 0 is a
-// chunk of GRAPH_SPC Arnoldi steps, kind 1 closes a cycle and opens the next (b and x are
+// chunk of chunk_steps() Arnoldi steps, kind 1 closes a cycle and opens the next (b and x are
 // part of the key, their addresses being baked into the graph).
 template <class T>
 static hipGraphExec_t cycle_graph(Krylov &K, const KOps<T> &ops, const GmresParams &p, int kind, const T *b, T *x,
@@ -186,13 +193,14 @@ static hipGraphExec_t cycle_graph(Krylov &K, const KOps<T> &ops, const GmresPara
     if (s.exec && s.owner == ops.owner && s.orth == p.orth && s.max_iter == p.max_iter && s.cplx == p.cplx &&
         s.pkind == ops.pkind && (kind == 0 || (s.b == (const void *)b && s.x == (const void *)x)))
         return s.exec;
+    const int spc = chunk_steps(ops);
     if (s.exec) (void)hipGraphExecDestroy(s.exec);
     if (s.graph) (void)hipGraphDestroy(s.graph);
     s = Krylov::GraphSlot{};
     THM_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     try {
         if (kind == 0) {
-            for (int i = 0; i < Krylov::GRAPH_SPC; ++i) arnoldi_step<T>(K, ops, p, Krylov::GRAPH_SPC, st);
+            for (int i = 0; i < spc; ++i) arnoldi_step<T>(K, ops, p, spc, st);
         } else {
             cycle_close<T>(K, ops, x, st);
             cycle_open<T>(K, ops, p, b, x, st);
@@ -262,15 +270,16 @@ void gmres_run(Krylov &K, const KOps<T> &ops, const T *b, T *x, const int32_t *m
         }
         return;
     }
-    // graph replay: a cycle is ceil(m / GRAPH_SPC) chunk graphs (steps past a system's end
-    // of cycle find it inactive and do nothing) and one close-and-reopen graph.  The finish
-    // kernels of chunk c leave the systems' flags in host slot c mod NEV; the host checks
-    // chunk c - 1 while chunk c runs, and the running flags once per cycle.
+    // graph replay: a cycle is ceil(m / spc) chunk graphs (steps past a system's end of cycle
+    // find it inactive and do nothing) and one close-and-reopen graph.  The finish kernels of
+    // chunk c leave the systems' flags in host slot c mod NEV; the host checks chunk c - 1
+    // while chunk c runs, and the running flags once per cycle.
     hipGraphExec_t chunk = cycle_graph<T>(K, ops, p, 0, b, x, st);
     hipGraphExec_t turn = cycle_graph<T>(K, ops, p, 1, b, x, st);
     cycle_open<T>(K, ops, p, b, x, st);
     THM_HIP(hipStreamSynchronize(st));
-    const int nchunks = (m + Krylov::GRAPH_SPC - 1) / Krylov::GRAPH_SPC;
+    const int spc = chunk_steps(ops);
+    const int nchunks = (m + spc - 1) / spc;
     static_assert(Krylov::NEV >= 4, "chunk flag slots in flight must not wrap");
     while (any_set(K.pinned_run, ns)) {
         for (int c = 0; c < nchunks; ++c) {
@@ -729,18 +738,33 @@ void Ctx::build_full() {
     d.m32 = full.m32.p;
     if (maxr_rep > 0) {
         // S_G: K^{-1} applied to unit vectors on Gamma, columns 2k and 2k + 1 from the real and
-        // imaginary parts of one right-hand side.  A temporary batch holds Q copies of every
-        // representative; the copies share its factor and form one member group of the apply,
-        // so one FP64 application yields 2Q columns of every representative while each factor
-        // matrix is read once per 16 copies.
+        // imaginary parts of one right-hand side.  A temporary batch holds Q copies of each
+        // representative of a chunk; the copies share its factor and form one member group of the
+        // apply, so one FP64 application yields 2Q columns of every representative of the chunk
+        // while each factor matrix is read once per 16 copies.  Chunks bound the temporary
+        // batch to TMP_DOFS complex DoFs (its vectors, not the factors, which are shared).
         DBuf<double> Sg(std::max<int64_t>(mtot, 1));
-        {
-            const int Q = (int)std::min<int64_t>(16, (maxr_rep + 1) / 2);
+        constexpr int64_t TMP_DOFS = int64_t(8) << 20;
+        std::vector<int> all_reps;
+        for (int s = 0; s < ns; ++s)
+            if (isrep[s]) all_reps.push_back(s);
+        for (size_t c0 = 0; c0 < all_reps.size();) {
+            int64_t rmax = 0, dofs = 0;
+            size_t c1 = c0;
+            while (c1 < all_reps.size()) {
+                const int s = all_reps[c1];
+                const int64_t q = std::min<int64_t>(16, (std::max(rmax, full.r[s]) + 1) / 2);
+                if (c1 > c0 && (dofs + sys[s]->n) * q > TMP_DOFS) break;
+                rmax = std::max(rmax, full.r[s]);
+                dofs += sys[s]->n;
+                ++c1;
+            }
+            const int Q = (int)std::min<int64_t>(16, (rmax + 1) / 2);
             std::vector<thm_system *> tsys;
             std::vector<int64_t> tgoff(1, 0), tsoff;
             std::vector<int32_t> tgam, tk;
-            for (int s = 0; s < ns; ++s) {
-                if (!isrep[s]) continue;
+            for (size_t c = c0; c < c1; ++c) {
+                const int s = all_reps[c];
                 for (int q = 0; q < Q; ++q) {
                     tsys.push_back(sys[s]);
                     tgam.insert(tgam.end(), gam.begin() + goff[s], gam.begin() + goff[s + 1]);
@@ -764,7 +788,7 @@ void Ctx::build_full() {
             DBuf<double> xin(T.K.B.Ltot), zout(T.K.B.Ltot);
             THM_HIP(hipMemsetAsync(xin.p, 0, sizeof(double) * xin.n, st));
             const int nt = T.ns;
-            for (int64_t k = 0; 2 * k < maxr_rep; k += Q) {
+            for (int64_t k = 0; 2 * k < rmax; k += Q) {
                 launch_full_unit(td, nt, nullptr, T.K.B.off.p, dtk.p, (int)k, 1.0, xin.p, st);
                 launch_prec_apply<double>(T.P, T.P.d64.p, T.K.B.off.p, nt, nullptr, xin.p, zout.p, T.ws64.p,
                                           T.ys64.p, T.tw64.p, st);
@@ -772,6 +796,7 @@ void Ctx::build_full() {
                 launch_full_unit(td, nt, nullptr, T.K.B.off.p, dtk.p, (int)k, 0.0, xin.p, st);
             }
             THM_HIP(hipStreamSynchronize(st));
+            c0 = c1;
         }
         // M = I + i C_G S_G in real form, inverted by Gauss-Jordan, then stored complex.  The
         // representatives are inverted in batches of at most INV_BATCH_ELEMS matrix entries

@@ -71,6 +71,10 @@ struct thm_system {
     thm::DBuf<int32_t> ncell;
     thm::DBuf<double> mu_d, eps_d;
     thm::DBuf<double> kel, kraw, kval, craw, cval;
+    // tangential trace mass blocks of the sides carrying C (sides_c order, nf x nf each) and the
+    // range of sides_c of each (axis, side) group (DDM interface sides with S = s 1 add to K)
+    thm::DBuf<double> cside;
+    int cside_lo[6] = {0, 0, 0, 0, 0, 0}, cside_hi[6] = {0, 0, 0, 0, 0, 0};
     thm::DBuf<float> kval32, cval32;
     thm::DBuf<int32_t> sl_ptr, sl_col, sl_src, sl_row;  // K in SELL-64 (see MatDesc)
     thm::DBuf<double> sl_val;

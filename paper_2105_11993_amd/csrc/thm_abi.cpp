@@ -156,6 +156,8 @@ static void validate(const thm_problem *p) {
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(p->inc_dir[a]) || !std::isfinite(p->inc_pol_re[a]) || !std::isfinite(p->inc_pol_im[a]))
             fail(THM_EINVAL, "incident field parameters must be finite");
+    if (!std::isfinite(p->transmission[0]) || !std::isfinite(p->transmission[1]))
+        fail(THM_EINVAL, "transmission factor must be finite");
 }
 
 // ---------------------------------------------------------------- Dirichlet projection (Jacobi-PCG)
@@ -253,6 +255,16 @@ static void assemble_K(thm_system &S, hipStream_t st) {
     const Topo &t = S.topo;
     launch_element_matrices(t.dim, t.n_cells, t.n_loc, S.tcell, S.h.p, S.mu_d.p, S.eps_d.n ? S.eps_d.p : nullptr,
                             S.prob.omega, S.kel.p, st);
+    // DDM interface sides with S = s 1 carry i k w s M_Sigma: its real part -k w Im(s) M_Sigma
+    // belongs to K (added to the element matrices, so the factorisation sees it too)
+    const double s_im = S.prob.transmission[1];
+    if (S.iface_sides && s_im != 0.0) {
+        const double coef = -S.prob.kappa * S.prob.omega * s_im;
+        for (int g = 0; g < 2 * t.dim; ++g)
+            if ((S.iface_sides >> g) & 1u)
+                launch_side_to_elem(S.cside_lo[g], S.cside_hi[g], S.sc_cell.p, S.sc_axis.p, S.sc_side.p, S.side_fn.p,
+                                    S.nf, t.n_loc, coef, S.cside.p, S.kel.p, st);
+    }
     const int64_t nnz = (int64_t)S.K.col.size();
     launch_gather(nnz, S.k_gptr.p, S.k_gsrc.p, S.kel.p, 1.0, S.kraw.p, st);
     THM_HIP(hipMemcpyAsync(S.kval.p, S.kraw.p, sizeof(double) * nnz, hipMemcpyDeviceToDevice, st));
@@ -265,6 +277,7 @@ static void assemble_system(thm_system &S, const thm_problem &p, uint32_t iface_
     S.prob = p;
     S.prob.mu = nullptr;
     S.prob.eps = nullptr;
+    if (S.prob.transmission[0] == 0.0 && S.prob.transmission[1] == 0.0) S.prob.transmission[0] = 1.0;
     S.iface_sides = iface_sides;
     Topo &t = S.topo;
     t.build(p.dim, p.degree, p.cells, p.box_lo, p.box_hi);
@@ -279,8 +292,10 @@ static void assemble_system(thm_system &S, const thm_problem &p, uint32_t iface_
     for (int axis = 0; axis < t.dim; ++axis)
         for (int side = 0; side < 2; ++side) {
             const bool inc = (p.inc_faces >> (2 * axis + side)) & 1u;
+            S.cside_lo[2 * axis + side] = (int)S.sides_c.size();
             for (int64_t c = 0; c < t.n_cells; ++c)
                 if (t.cell_on_side(c, axis, side)) (inc ? S.sides_inc : S.sides_c).push_back({(int32_t)c, axis, side});
+            S.cside_hi[2 * axis + side] = (int)S.sides_c.size();
         }
     S.nf = (int)t.side_fns[0].size();
     S.dir.assign(S.n, 0);
@@ -358,6 +373,13 @@ static void assemble_system(thm_system &S, const thm_problem &p, uint32_t iface_
     fe_tables_cell(t.dim, t.p, t.p + 2, S.fns.p, nl, S.tcell, st);
     fe_tables_side(t.dim, t.p, t.p + 2, 0, 0, S.fns.p, nl, S.tside, st);
     fe_tables_side(t.dim, t.p, 10, 0, 0, S.fns.p, nl, S.tload, st);
+    // tangential trace masses of the sides carrying C
+    const int nsc = (int)S.sides_c.size();
+    S.cside.alloc((size_t)std::max(nsc, 1) * S.nf * S.nf);
+    {
+        const FeTables *ts[6] = {&S.tside, &S.tside, &S.tside, &S.tside, &S.tside, &S.tside};
+        launch_side_mass(t.dim, nsc, S.sc_axis.p, S.sc_side.p, S.side_fn.p, S.nf, nl, ts, S.h.p, S.cside.p, st);
+    }
     // K
     const int64_t nnz = (int64_t)S.K.col.size();
     S.kel.alloc((size_t)t.n_cells * nl * nl);
@@ -375,18 +397,19 @@ static void assemble_system(thm_system &S, const thm_problem &p, uint32_t iface_
         S.sl_val32.alloc(std::max<size_t>(src.size(), 1));
     }
     assemble_K(S, st);
-    // C = k w (M_inf + M_Sigma)
+    // C = k w (M_inf + Re(s) M_Sigma)
     const int64_t nnzc = (int64_t)S.C.col.size();
     S.craw.alloc(std::max<int64_t>(nnzc, 1));
     S.cval.alloc(std::max<int64_t>(nnzc, 1));
     S.cval32.alloc(std::max<int64_t>(nnzc, 1));
-    {
-        const int nsc = (int)S.sides_c.size();
+    if (iface_sides && S.prob.transmission[0] != 1.0) {
         DBuf<double> cblk((size_t)std::max(nsc, 1) * S.nf * S.nf);
-        const FeTables *ts[6] = {&S.tside, &S.tside, &S.tside, &S.tside, &S.tside, &S.tside};
-        launch_side_mass(t.dim, nsc, S.sc_axis.p, S.sc_side.p, S.side_fn.p, S.nf, nl, ts, S.h.p, cblk.p, st);
+        launch_side_scale(nsc, S.sc_axis.p, S.sc_side.p, iface_sides, S.nf, S.prob.transmission[0], S.cside.p, cblk.p,
+                          st);
         launch_gather(nnzc, S.c_gptr.p, S.c_gsrc.p, cblk.p, p.kappa * p.omega, S.craw.p, st);
         THM_HIP(hipStreamSynchronize(st));
+    } else {
+        launch_gather(nnzc, S.c_gptr.p, S.c_gsrc.p, S.cside.p, p.kappa * p.omega, S.craw.p, st);
     }
     THM_HIP(hipMemcpyAsync(S.cval.p, S.craw.p, sizeof(double) * nnzc, hipMemcpyDeviceToDevice, st));
     launch_dirichletize(S.n, S.c_rowptr.p, S.c_col.p, S.dir_d.p, S.cval.p, 0, st);
@@ -696,7 +719,8 @@ struct DdmRun {
     void update(const double *Gv, int mode, double *out) {
         sync_inner();
         launch_ddm_update(D.nent, D.ent_sys.p, D.ent_row.p, D.ent_rev.p, D.ent_mptr.p, D.m_col.p, D.m_val.p, X(), Gv,
-                          G.prob.kappa * G.prob.omega, mode, out, st);
+                          G.prob.kappa * G.prob.omega, G.prob.transmission[0], G.prob.transmission[1], mode, out,
+                          st);
     }
     double global_residual(double *Eout) {
         sync_inner();

@@ -64,6 +64,30 @@ def test_ddm_gmres_reaches_global_solution(thm, case):
     assert rel(E5, Eg) <= 1e-8
 
 
+TS_CASES = [(2, 8, 1, (2, 2, 1), 6.0, 0.6 + 0.8j), (2, 8, 2, (2, 1, 1), 8.0, 2.0),
+            (3, 4, 1, (2, 1, 1), 5.0, 1.5 - 0.5j)]
+
+
+@pytest.mark.parametrize("case", TS_CASES, ids=lambda c: f"d{c[0]}m{c[1]}p{c[2]}s{c[5]}")
+def test_ddm_scaled_transmission_matches_oracle(thm, case):
+    """Transmission operator S = s 1 with s != 1 (interface terms i k w s M_Sigma and the update
+    -2 i k w s M_Sigma E): the Jacobi iterates equal the oracle's with the same s, and the fixed
+    point reached by the interface GMRES is the global LU solution."""
+    d = dict(_ddm_case(*case[:5], seed=9), transmission=case[5])
+    print("case", case, flush=True)
+    S = thm.thm_assemble(d)
+    D = ddm.DDM(problem(d))
+    ref, _ = D.jacobi(2)
+    for k in (1, 2):
+        o = thm.default_opts(ddm_outer=thm.THM_DDM_JACOBI, max_outer=k, rtol=0.0, inner_rtol=1e-13)
+        E, st = thm.thm_ddm_solve(S, o)
+        assert rel(E.cpu().numpy(), ref[k - 1]) <= 1e-10, k
+    Eg = system.solve_lu(system.assemble(problem(d)))
+    E, st = ddm_fp64(thm, S)
+    assert st["rel_residual"] <= 1e-12
+    assert rel(E, Eg) <= 1e-10
+
+
 def test_ddm_single_subdomain_equals_single_domain(thm):
     d = workloads.c1()
     S = thm.thm_assemble(d)
