@@ -75,6 +75,9 @@ def parse():
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"),
                     help="summarize two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this script and exit")
+    ap.add_argument("--summarize-mfma", metavar="COUNTER_CSV",
+                    help="summarize a rocprofv3 --pmc MfmaUtil MfmaFlopsF32 MfmaFlopsF64 run (its "
+                         "counter_collection.csv) per kernel and exit")
     return ap.parse_args()
 
 
@@ -197,6 +200,33 @@ def summarize_pmc(fetch_dir, write_dir, out_json):
     with open(out_json, "w") as f:
         json.dump(rec, f, indent=1)
     print(json.dumps(rec, indent=1))
+
+
+def summarize_mfma(path, last=PRECOND_LAUNCHES):
+    """Per kernel of a rocprofv3 counter run with MfmaUtil, MfmaFlopsF32 and MfmaFlopsF64: the
+    dispatches' total duration (counter-run timestamps), MFMA flops (the MOPS counters x 512),
+    achieved TFLOP/s and the duration-weighted MfmaUtil (MFMA busy cycles over GPU-active cycles
+    times SIMDs, in %).  For k_bcr_mfma<float> only the last `last` dispatches count (the timed
+    preconditioner applications at the end of the run, every member active)."""
+    import collections
+    import csv
+    per = {}
+    for r in csv.DictReader(open(path)):
+        key = (int(r["Dispatch_Id"]), r["Kernel_Name"].split("(")[0])
+        e = per.setdefault(key, {"t": (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9})
+        e[r["Counter_Name"]] = float(r["Counter_Value"])
+    byk = collections.defaultdict(list)
+    for (_, k), v in sorted(per.items()):
+        byk[k].append(v)
+    out = {}
+    for k, lst in byk.items():
+        sel = lst[-last:] if "k_bcr_mfma<float" in k else lst
+        t = sum(x["t"] for x in sel)
+        fl = sum(x.get("MfmaFlopsF32", 0.0) + x.get("MfmaFlopsF64", 0.0) for x in sel)
+        mu = sum(x.get("MfmaUtil", 0.0) * x["t"] for x in sel) / max(t, 1e-300)
+        out[k] = {"dispatches": len(sel), "s": t, "mfma_flops": fl, "tflops": fl / max(t, 1e-300) / 1e12,
+                  "mfma_util_pct": mu}
+    print(json.dumps(out, indent=1))
 
 
 def measured_traffic(algorithmic_bytes_per_launch):
@@ -622,6 +652,9 @@ def main():
     args = parse()
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc)
+        return
+    if args.summarize_mfma:
+        summarize_mfma(args.summarize_mfma)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not part of "
