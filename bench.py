@@ -786,7 +786,8 @@ def main():
     if inf["ddm_spmv_groups"] >= 0:
         spmv_batch = {"variant_fp64": inf["ddm_spmv_variant"], "groups": inf["ddm_spmv_groups"]}
         for name, prec in (("fp64", thm.THM_FP64), ("fp32", thm.THM_FP32_IR)):
-            for vname, v in (("sell", thm.THM_SPMV_SELL), ("grouped", thm.THM_SPMV_SELL_GROUP)):
+            for vname, v in (("sell", thm.THM_SPMV_SELL), ("grouped", thm.THM_SPMV_SELL_GROUP),
+                             ("grouped_interleaved", thm.THM_SPMV_SELL_GROUP_IL)):
                 ms, by = thm.thm_time_spmv_batch(S, prec, v, reps=50)
                 spmv_batch[f"{name}_{vname}"] = {"ms": ms, "bytes": by, "GBps": by / ms / 1e6}
         log(args, f"spmv batch: {spmv_batch}")

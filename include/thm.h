@@ -298,6 +298,13 @@ thm_status thm_time_spmv_systems(int32_t nsys, thm_system *const *sys, int32_t p
  * K is read once per group instead of once per system; each member's C is applied from
  * its own rows.  Results are bitwise those of code 19. */
 #define THM_SPMV_SELL_GROUP 20
+/* Grouped SELL-64 reading every member's vector from one member-interleaved copy (code 29):
+ * chosen for a batch with shared K, the preconditioner of an Arnoldi step writes its output
+ * straight into that copy (member j's value at row r next to the other members' values of row
+ * r) and the product reads each row's values of all members as one contiguous run; outside
+ * the Arnoldi step the batch uses code 20.  The same bits as code 20.  thm_time_spmv_batch
+ * times the product alone on the copy's current contents. */
+#define THM_SPMV_SELL_GROUP_IL 29
 
 /* Pin the SpMV variant of the single-system context of `sys` (the one used by
  * thm_gmres_solve on {sys}, thm_apply_operator and thm_time_spmv) and, once a DDM solve

@@ -70,6 +70,7 @@ EXPORTS = ["thm_default_opts", "thm_assemble", "thm_gmres_solve", "thm_ddm_solve
            "thm_time_spmv_systems", "thm_system_release_workspaces", "thm_apply_precond_noalloc"]
 THM_SPMV_SELL = 19
 THM_SPMV_SELL_GROUP = 20
+THM_SPMV_SELL_GROUP_IL = 29  # timing code of the grouped product on the member-interleaved copy
 SPMV_VARIANTS = [21, 41, 81, 161, 321, 641, 24, 44, 84, 164, 324, THM_SPMV_SELL, THM_SPMV_SELL_GROUP]
 
 

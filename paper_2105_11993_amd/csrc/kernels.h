@@ -28,6 +28,9 @@ constexpr int SPMV_SELL = 19;     // SpMV variant code of the SELL-64 kernel (25
 // Grouped SELL-64 (variant code SPMV_SELL_GROUP): systems of a batch with the same K share
 // one read of it per product.  A group holds at most SPMV_GMAX systems.
 constexpr int SPMV_SELL_GROUP = 20;
+// The grouped product reading x from the member-interleaved copy that the preconditioner
+// writes in an Arnoldi step (chosen explicitly; elsewhere the batch uses SPMV_SELL_GROUP).
+constexpr int SPMV_SELL_GROUP_IL = 29;
 constexpr int SPMV_GMAX = 16;
 struct SpmvGroup {
     int32_t rep;                 // system whose SELL arrays hold the shared K
@@ -35,6 +38,9 @@ struct SpmvGroup {
     int32_t npad;                // nm rounded up to 4, 8, 12 or 16 (npad / 4 waves per slice)
     int32_t mem[SPMV_GMAX];      // member system indices
     const uint8_t *crow;         // per row of K: 1 if some member's C row has entries
+    // member-interleaved copy of the group's vectors (complex entries): member j's value at row r
+    // lies at xoff + r npad + j, so one row of K meets every member's value in one contiguous run
+    int64_t xoff;
 };
 // Host: SELL-64 layout of a CSR pattern; src[e] = CSR index of entry e, or -1 (padding).
 void sell_build(int64_t n, const std::vector<int32_t> &rowptr, const std::vector<int32_t> &col,
@@ -112,6 +118,11 @@ void launch_spmv(int lpr, const MatDesc *mats, const int64_t *off, const Sched &
 template <class T>
 void launch_spmv_group(const MatDesc *mats, const int64_t *off, const SpmvGroup *groups, const Sched &sc, int ng,
                        const int32_t *mask, const T *x, T *y, const T *b, float csign, hipStream_t st);
+// The same product with x read from the member-interleaved copy xi (see SpmvGroup::xoff):
+// the same sums in the same order, so the same bits.
+template <class T>
+void launch_spmv_group_i(const MatDesc *mats, const int64_t *off, const SpmvGroup *groups, const Sched &sc, int ng,
+                         const int32_t *mask, const T *xi, T *y, float csign, hipStream_t st);
 template <class T>
 void launch_dots(const Batch &B, const int32_t *mask, const int32_t *jcnt, const T *V, int64_t ld, const T *w,
                  double *part, int cplx, hipStream_t st);
@@ -246,9 +257,19 @@ template <class T>
 void launch_bcr_phases(const PrecBatch &P, const int32_t *mask, T *ws, T *ys, hipStream_t st);
 // x = diag(K, K)^{-1} r for every system of the batch; ws, ys: skeleton work vectors
 // (PrecBatch::Stot scalars), tw: condensation terms (2 PrecBatch::Ttot scalars).
+// Output in the member-interleaved layout of the grouped SpMV instead of the systems' own
+// vectors: the SpMV groups, a schedule of IL_TILE DoFs of a group per block, the copy.
+constexpr int IL_TILE = 64;
+template <class T>
+struct IlOut {
+    const SpmvGroup *groups;
+    const Sched *sched;
+    int ng;
+    T *xi;
+};
 template <class T>
 void launch_prec_apply(const PrecBatch &P, const PrecDesc *d, const int64_t *off, int ns, const int32_t *mask,
-                       const T *r, T *x, T *ws, T *ys, T *tw, hipStream_t st);
+                       const T *r, T *x, T *ws, T *ys, T *tw, hipStream_t st, const IlOut<T> *il = nullptr);
 
 // ---- complete inverse (K + iC)^{-1} through K^{-1} and a boundary correction (kernels_full.hip)
 struct FullDesc {

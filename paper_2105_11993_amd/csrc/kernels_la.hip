@@ -227,7 +227,47 @@ template void launch_spmv<float>(int, const MatDesc *, const int64_t *, const Sc
 // the sibling waves hit the caches.  The sum over a row runs in the same order as in
 // k_spmv_sell, so both variants give the same bits.  Each member's boundary operator C is
 // applied from its own CSR, on the rows where some member has C entries.
-template <class T, int U>
+// The four members' values of one x entry.  Per-member vectors (IL = false): four gathers.
+// Member-interleaved copy (IL = true): the four values are one contiguous 4-complex run.
+template <class T, bool IL>
+struct GroupX;
+template <class T>
+struct GroupX<T, false> {
+    using T2 = typename V2<T>::t;
+    const T2 *x[4];
+    __device__ __forceinline__ GroupX(const SpmvGroup &G, int j0, int nmw, const int64_t *off, const T *xb) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) x[j] = reinterpret_cast<const T2 *>(xb + off[G.mem[j0 + min(j, nmw - 1)]]);
+    }
+    __device__ __forceinline__ void load(int32_t c, T2 (&v)[4]) const {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = x[j][c];
+    }
+    __device__ __forceinline__ T2 load1(int32_t c, int j) const { return x[j][c]; }
+};
+template <class T>
+struct GroupX<T, true> {
+    using T2 = typename V2<T>::t;
+    typedef T vec4 __attribute__((ext_vector_type(4)));
+    const T *x;
+    int64_t ld;  // scalars per row of the interleaved copy
+    __device__ __forceinline__ GroupX(const SpmvGroup &G, int j0, int, const int64_t *, const T *xib)
+        : x(xib + 2 * (G.xoff + j0)), ld(2 * (int64_t)G.npad) {}
+    __device__ __forceinline__ void load(int32_t c, T2 (&v)[4]) const {
+        // 8 scalars of members j0 .. j0 + 3 (16-byte aligned: npad, j0 and xoff are multiples of 4)
+        const vec4 *p = reinterpret_cast<const vec4 *>(x + c * ld);
+        const vec4 a = p[0], b = p[1];
+        v[0] = T2{a[0], a[1]};
+        v[1] = T2{a[2], a[3]};
+        v[2] = T2{b[0], b[1]};
+        v[3] = T2{b[2], b[3]};
+    }
+    __device__ __forceinline__ T2 load1(int32_t c, int j) const {
+        return reinterpret_cast<const T2 *>(x + c * ld)[j];
+    }
+};
+
+template <class T, int U, bool IL>
 __device__ __forceinline__ void spmv_group_slice(const MatDesc *__restrict__ mats, const int64_t *__restrict__ off,
                                                  const SpmvGroup &G, int j0, const MatDesc &m, int64_t slice,
                                                  const int32_t *__restrict__ mask, const T *__restrict__ xb,
@@ -240,9 +280,7 @@ __device__ __forceinline__ void spmv_group_slice(const MatDesc *__restrict__ mat
     const int32_t e0 = m.sl_ptr[slice], w = (m.sl_ptr[slice + 1] - e0) / SELL_C;
     const int32_t *cp = m.sl_col + e0 + lane;
     const T *vp = reinterpret_cast<const T *>(m.sl_val) + e0 + lane;
-    const T2 *x[MB];
-#pragma unroll
-    for (int j = 0; j < MB; ++j) x[j] = reinterpret_cast<const T2 *>(xb + off[G.mem[j0 + min(j, nmw - 1)]]);
+    const GroupX<T, IL> x(G, j0, nmw, off, xb);
     T ar[MB], ai[MB];
 #pragma unroll
     for (int j = 0; j < MB; ++j) ar[j] = ai[j] = 0;
@@ -255,27 +293,26 @@ __device__ __forceinline__ void spmv_group_slice(const MatDesc *__restrict__ mat
             c[u] = cp[(k + u) * SELL_C];
             v[u] = vp[(k + u) * SELL_C];
         }
-        T2 xv[MB][U];
+        T2 xv[U][MB];
 #pragma unroll
-        for (int j = 0; j < MB; ++j)
-#pragma unroll
-            for (int u = 0; u < U; ++u) xv[j][u] = x[j][c[u]];
+        for (int u = 0; u < U; ++u) x.load(c[u], xv[u]);
 #pragma unroll
         for (int j = 0; j < MB; ++j)
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                ar[j] += v[u] * xv[j][u].x;
-                ai[j] += v[u] * xv[j][u].y;
+                ar[j] += v[u] * xv[u][j].x;
+                ai[j] += v[u] * xv[u][j].y;
             }
     }
     for (; k < w; ++k) {
         const T v = vp[k * SELL_C];
         const int32_t c = cp[k * SELL_C];
+        T2 xv[MB];
+        x.load(c, xv);
 #pragma unroll
         for (int j = 0; j < MB; ++j) {
-            const T2 xv = x[j][c];
-            ar[j] += v * xv.x;
-            ai[j] += v * xv.y;
+            ar[j] += v * xv[j].x;
+            ai[j] += v * xv[j].y;
         }
     }
     if (row < 0) return;
@@ -288,9 +325,9 @@ __device__ __forceinline__ void spmv_group_slice(const MatDesc *__restrict__ mat
             const T *cv = reinterpret_cast<const T *>(mj.cval);
             for (int32_t q = mj.crowptr[row]; q < mj.crowptr[row + 1]; ++q) {
                 const T c = sg * cv[q];
-                const T2 xv = x[j][mj.ccol[q]];
-                ar[j] -= c * xv.y;
-                ai[j] += c * xv.x;
+                const T2 xq = x.load1(mj.ccol[q], j);
+                ar[j] -= c * xq.y;
+                ai[j] += c * xq.x;
             }
         }
     }
@@ -311,8 +348,9 @@ __device__ __forceinline__ void spmv_group_slice(const MatDesc *__restrict__ mat
     }
 }
 
-// Block schedule: npad / 4 consecutive waves per slice (see SpmvGroup).
-template <class T>
+// Block schedule: npad / 4 consecutive waves per slice (see SpmvGroup).  IL: x is the
+// member-interleaved copy (see SpmvGroup::xoff) instead of the per-system vectors.
+template <class T, bool IL>
 __global__ void __launch_bounds__(256) k_spmv_sell_group(const MatDesc *__restrict__ mats,
                                                          const int64_t *__restrict__ off,
                                                          const SpmvGroup *__restrict__ groups,
@@ -334,16 +372,28 @@ __global__ void __launch_bounds__(256) k_spmv_sell_group(const MatDesc *__restri
         if (!any) return;
     }
     constexpr int U = sizeof(T) == 4 ? 4 : 2;
-    spmv_group_slice<T, U>(mats, off, G, j0, m, slice, mask, xb, yb, bb, csign);
+    spmv_group_slice<T, U, IL>(mats, off, G, j0, m, slice, mask, xb, yb, bb, csign);
 }
 
 template <class T>
 void launch_spmv_group(const MatDesc *mats, const int64_t *off, const SpmvGroup *groups, const Sched &sc, int ng,
                        const int32_t *mask, const T *x, T *y, const T *b, float csign, hipStream_t st) {
     if (!sc.nblocks) return;
-    k_spmv_sell_group<T><<<sc.nblocks, 256, 0, st>>>(mats, off, groups, sc.blkoff.p, ng, mask, x, y, b, csign);
+    k_spmv_sell_group<T, false><<<sc.nblocks, 256, 0, st>>>(mats, off, groups, sc.blkoff.p, ng, mask, x, y, b, csign);
     THM_HIP(hipGetLastError());
 }
+template <class T>
+void launch_spmv_group_i(const MatDesc *mats, const int64_t *off, const SpmvGroup *groups, const Sched &sc, int ng,
+                         const int32_t *mask, const T *xi, T *y, float csign, hipStream_t st) {
+    if (!sc.nblocks) return;
+    k_spmv_sell_group<T, true><<<sc.nblocks, 256, 0, st>>>(mats, off, groups, sc.blkoff.p, ng, mask, xi, y, nullptr,
+                                                           csign);
+    THM_HIP(hipGetLastError());
+}
+template void launch_spmv_group_i<double>(const MatDesc *, const int64_t *, const SpmvGroup *, const Sched &, int,
+                                          const int32_t *, const double *, double *, float, hipStream_t);
+template void launch_spmv_group_i<float>(const MatDesc *, const int64_t *, const SpmvGroup *, const Sched &, int,
+                                         const int32_t *, const float *, float *, float, hipStream_t);
 template void launch_spmv_group<double>(const MatDesc *, const int64_t *, const SpmvGroup *, const Sched &, int,
                                         const int32_t *, const double *, double *, const double *, float,
                                         hipStream_t);

@@ -625,26 +625,17 @@ __global__ void __launch_bounds__(64 * WPB, BcrOcc<T>::v) k_bcr_mfma(const BcrTa
         bcr_tile<T, WPB, 2>(tk, sh, rt * BCR_RT, mb, m1, memb, mask, wsb, ysb);
 }
 
-// x[g] = ys[pos(g)] on skeleton DoFs; interiors: x_i = Kii^{-1} r_i - F^T x_e.
+// Value of DoF g of system d's output: ys[pos(g)] on skeleton DoFs; interiors:
+// x_i = Kii^{-1} r_i - F^T x_e (r: the system's input, ys: its skeleton solution column).
 template <class T>
-__global__ void __launch_bounds__(256) k_cond_bwd(const PrecDesc *__restrict__ pd, const int64_t *__restrict__ off,
-                                                  const int64_t *__restrict__ soff, const int32_t *__restrict__ blkoff,
-                                                  int ns, const int32_t *__restrict__ mask, const T *__restrict__ rb,
-                                                  const T *__restrict__ ysb, T *__restrict__ xb) {
+__device__ __forceinline__ typename P2<T>::t cond_bwd_value(const PrecDesc &d, int64_t g, const T *__restrict__ r_s,
+                                                            const T *__restrict__ ys) {
     using T2 = typename P2<T>::t;
-    const int s = find_sys2(blkoff, ns, blockIdx.x);
-    if (mask && !mask[s]) return;
-    const PrecDesc &d = pd[s];
-    const int64_t g = (int64_t)(blockIdx.x - blkoff[s]) * 256 + threadIdx.x;
-    if (g >= d.n) return;
-    const T *ys = ysb + soff[s];
-    T2 *x = reinterpret_cast<T2 *>(xb + off[s]);
     if (g < d.cell_off) {
         const T *yp = ys + wv_pos(d.dof_pos[g], d.cs);
-        x[g] = T2{yp[0], yp[8]};
-        return;
+        return T2{yp[0], yp[8]};
     }
-    const T2 *r = reinterpret_cast<const T2 *>(rb + off[s]);
+    const T2 *r = reinterpret_cast<const T2 *>(r_s);
     const int gi = (int)(g - d.cell_off);
     const int64_t c = gi / d.n_int;
     const int m = gi - (int)c * d.n_int;
@@ -665,7 +656,69 @@ __global__ void __launch_bounds__(256) k_cond_bwd(const PrecDesc *__restrict__ p
         acc.x -= f * yp[0];
         acc.y -= f * yp[8];
     }
-    x[g] = acc;
+    return acc;
+}
+
+// x = the output of every system (one block per 256 DoFs of one system).
+template <class T>
+__global__ void __launch_bounds__(256) k_cond_bwd(const PrecDesc *__restrict__ pd, const int64_t *__restrict__ off,
+                                                  const int64_t *__restrict__ soff, const int32_t *__restrict__ blkoff,
+                                                  int ns, const int32_t *__restrict__ mask, const T *__restrict__ rb,
+                                                  const T *__restrict__ ysb, T *__restrict__ xb) {
+    using T2 = typename P2<T>::t;
+    const int s = find_sys2(blkoff, ns, blockIdx.x);
+    if (mask && !mask[s]) return;
+    const PrecDesc &d = pd[s];
+    const int64_t g = (int64_t)(blockIdx.x - blkoff[s]) * 256 + threadIdx.x;
+    if (g >= d.n) return;
+    reinterpret_cast<T2 *>(xb + off[s])[g] = cond_bwd_value<T>(d, g, rb + off[s], ysb + soff[s]);
+}
+
+// The same outputs written only to the member-interleaved copy of the grouped SpMV (see
+// SpmvGroup::xoff).  A block takes IL_TILE consecutive DoFs of every member of one group:
+// wave k computes the tile's DoFs of member k (the reads of k_cond_bwd), the tile is
+// transposed through LDS, and the block writes it as one contiguous run of the copy.
+// Padding slots (member index >= nm) and masked members receive zeros, so that every
+// write covers whole lines (the grouped SpMV ignores those members' results); a block
+// whose group has no active member returns at once.
+// blkoff: schedule of ceil(rows / IL_TILE) blocks per group; 64 SPMV_GMAX threads per block.
+template <class T>
+__global__ void __launch_bounds__(64 * SPMV_GMAX) k_cond_bwd_il(const PrecDesc *__restrict__ pd,
+                                                                const int64_t *__restrict__ off,
+                                                                const int64_t *__restrict__ soff,
+                                                                const SpmvGroup *__restrict__ groups,
+                                                                const int32_t *__restrict__ blkoff, int ng,
+                                                                const int32_t *__restrict__ mask,
+                                                                const T *__restrict__ rb, const T *__restrict__ ysb,
+                                                                T *__restrict__ xib) {
+    static_assert(IL_TILE == 64, "one wave per member and tile");
+    using T2 = typename P2<T>::t;
+    constexpr int LD = SPMV_GMAX + 1;  // LDS row stride (entries): spreads a wave's stores over the banks
+    __shared__ T2 tile[IL_TILE * LD];
+    const int gi = find_sys2(blkoff, ng, blockIdx.x);
+    const SpmvGroup &G = groups[gi];
+    const int npad = G.npad, nm = G.nm;
+    const int64_t n = pd[G.rep].n;  // members share K, hence the DoF count
+    const int64_t g0 = (int64_t)(blockIdx.x - blkoff[gi]) * IL_TILE;
+    if (mask && !__syncthreads_or((int)threadIdx.x < nm && mask[G.mem[threadIdx.x]])) return;
+    const int lane = (int)threadIdx.x & 63;
+    // the wave's member: uniform over the wave, so its descriptor loads stay scalar
+    const int k = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    if (k < npad) {
+        const int64_t g = g0 + lane;
+        T2 v{0, 0};
+        if (k < nm) {
+            const int s = G.mem[k];
+            if ((!mask || mask[s]) && g < n) v = cond_bwd_value<T>(pd[s], g, rb + off[s], ysb + soff[s]);
+        }
+        tile[lane * LD + k] = v;
+    }
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t >= IL_TILE * npad) return;
+    const int l = t / npad, kk = t - l * npad;
+    if (g0 + l >= n) return;
+    (reinterpret_cast<T2 *>(xib) + G.xoff + g0 * npad)[t] = tile[l * LD + kk];
 }
 
 template <class T>
@@ -761,20 +814,27 @@ void launch_repack(const std::vector<RepackDesc> &d, double *dst64, float *dst32
 
 template <class T>
 void launch_prec_apply(const PrecBatch &P, const PrecDesc *d, const int64_t *off, int ns, const int32_t *mask,
-                       const T *r, T *x, T *ws, T *ys, T *tw, hipStream_t st) {
+                       const T *r, T *x, T *ws, T *ys, T *tw, hipStream_t st, const IlOut<T> *il) {
     if (P.cfr.nblocks) k_cond_fr<T><<<P.cfr.nblocks, 256, 0, st>>>(d, off, P.toff.p, P.cfr.blkoff.p, ns, mask, r, tw);
     if (P.skel.nblocks)
         k_cond_fwd<T><<<P.skel.nblocks, 256, 0, st>>>(d, off, P.soff.p, P.toff.p, P.skel.blkoff.p, ns, mask, r, tw, ws);
     launch_bcr_phases<T>(P, mask, ws, ys, st);
-    if (P.dofs.nblocks)
+    if (il) {
+        if (il->sched->nblocks)
+            k_cond_bwd_il<T><<<il->sched->nblocks, 64 * SPMV_GMAX, 0, st>>>(d, off, P.soff.p, il->groups, il->sched->blkoff.p,
+                                                                 il->ng, mask, r, ys, il->xi);
+    } else if (P.dofs.nblocks) {
         k_cond_bwd<T><<<P.dofs.nblocks, 256, 0, st>>>(d, off, P.soff.p, P.dofs.blkoff.p, ns, mask, r, ys, x);
+    }
     THM_HIP(hipGetLastError());
 }
 
 template void launch_prec_apply<double>(const PrecBatch &, const PrecDesc *, const int64_t *, int, const int32_t *,
-                                        const double *, double *, double *, double *, double *, hipStream_t);
+                                        const double *, double *, double *, double *, double *, hipStream_t,
+                                        const IlOut<double> *);
 template void launch_prec_apply<float>(const PrecBatch &, const PrecDesc *, const int64_t *, int, const int32_t *,
-                                       const float *, float *, float *, float *, float *, hipStream_t);
+                                       const float *, float *, float *, float *, float *, hipStream_t,
+                                       const IlOut<float> *);
 
 
 }  // namespace thm

@@ -126,9 +126,14 @@ static void arnoldi_step(Krylov &K, const KOps<T> &ops, const GmresParams &p, in
     const int m = K.m;
     T *V = K.V<T>(), *w = K.w<T>(), *z = K.z<T>(), *cur = K.cur<T>();
     int32_t *act = K.active.p;
-    ops.prec(cur, z, act);
+    if (ops.apply_i) {
+        ops.prec_i(cur, z, act);
+        ops.apply_i(w, act);
+    } else {
+        ops.prec(cur, z, act);
+        ops.apply(z, w, nullptr, act);
+    }
     if (flexible(ops)) launch_scale<T, T>(B, act, nullptr, 0, z, K.Z<T>(), K.jcnt.p, B.Ltot, nullptr, st);
-    ops.apply(z, w, nullptr, act);
     const int ldh = 2 * (m + 1);
     launch_dots<T>(B, act, K.jcnt.p, V, B.Ltot, w, K.part.p, p.cplx, st);
     launch_reduce_cols(B, act, K.jcnt.p, 0, K.part.p, K.hcol.p, ldh, 0, st);
@@ -371,12 +376,21 @@ void Ctx::build_groups() {
     }
     ngroups = (int)rep.size();
     spmv_shared = false;
-    std::vector<int64_t> coff(ngroups + 1, 0), rows(ngroups), waves(ngroups);
+    std::vector<int64_t> coff(ngroups + 1, 0), rows(ngroups), waves(ngroups), xoff(ngroups + 1, 0);
     for (int g = 0; g < ngroups; ++g) {
         rows[g] = sys[rep[g]]->n;
         waves[g] = (rows[g] + SELL_C - 1) / SELL_C * (int64_t)(((int)mem[g].size() + 3) / 4);
         coff[g + 1] = coff[g] + ((rows[g] + 255) & ~int64_t(255));
         spmv_shared |= mem[g].size() > 1;
+        // interleaved copy: rows x npad complex entries per group, groups 16-entry aligned
+        xoff[g + 1] = (xoff[g] + rows[g] * (((int64_t)mem[g].size() + 3) & ~int64_t(3)) + 15) & ~int64_t(15);
+    }
+    xi_total = xoff[ngroups];
+    {
+        // interleaved preconditioner output: blocks of IL_TILE DoFs of every member of a group
+        std::vector<int64_t> nb(ngroups);
+        for (int g = 0; g < ngroups; ++g) nb[g] = (rows[g] + IL_TILE - 1) / IL_TILE;
+        ilsched.build(nb, 1, st);
     }
     std::vector<uint8_t> crow(coff[ngroups], 0);
     for (int g = 0; g < ngroups; ++g)
@@ -394,6 +408,7 @@ void Ctx::build_groups() {
         G.npad = (G.nm + 3) & ~3;
         for (int j = 0; j < SPMV_GMAX; ++j) G.mem[j] = mem[g][std::min(j, G.nm - 1)];
         G.crow = sgcrow.p + coff[g];
+        G.xoff = xoff[g];
     }
     sgroups.upload(h, st);
     hgroups = h;
@@ -404,7 +419,7 @@ void Ctx::build_groups() {
 template <class T>
 void Ctx::spmv(int v, const int32_t *mask, const T *x, T *y, const T *b, float csign) {
     const MatDesc *m = sizeof(T) == 8 ? mat64.p : mat32.p;
-    if (v == SPMV_SELL_GROUP) {
+    if (v == SPMV_SELL_GROUP || v == SPMV_SELL_GROUP_IL) {  // outside an Arnoldi step: per-system x
         launch_spmv_group<T>(m, K.B.off.p, sgroups.p, gsched, ngroups, mask, x, y, b, csign, st);
         return;
     }
@@ -457,6 +472,7 @@ void Ctx::build_prec() {
         d.cond_ptr = S.Lcond_ptr.p;
         d.cond_cell = S.Lcond_cell.p;
         d.cond_loc = S.Lcond_loc.p;
+
         p32[i] = d;
         d.kiinv = f.kiinv.p;
         d.F = f.F.p;
@@ -866,6 +882,17 @@ void Ctx::build_full() {
     full.ready = true;
 }
 
+void Ctx::ensure_xi(bool f32) {
+    if (f32 && !xi32.n) {
+        xi32.alloc(2 * std::max<int64_t>(xi_total, 1));
+        THM_HIP(hipMemsetAsync(xi32.p, 0, sizeof(float) * xi32.n, st));
+    }
+    if (!f32 && !xi64.n) {
+        xi64.alloc(2 * std::max<int64_t>(xi_total, 1));
+        THM_HIP(hipMemsetAsync(xi64.p, 0, sizeof(double) * xi64.n, st));
+    }
+}
+
 KOps<double> Ctx::ops64(float csign, bool with_prec, int pkind) {
     if (with_prec) build_prec();
     if (with_prec && pkind == 1) build_full();
@@ -873,6 +900,16 @@ KOps<double> Ctx::ops64(float csign, bool with_prec, int pkind) {
     o.apply = [this, csign](const double *x, double *y, const double *b, const int32_t *mask) {
         spmv<double>(lpr64, mask, x, y, b, csign);
     };
+    if (with_prec && pkind == 0 && lpr64 == SPMV_SELL_GROUP_IL && spmv_shared) {
+        ensure_xi(false);
+        o.prec_i = [this](const double *x, double *y, const int32_t *mask) {
+            const IlOut<double> il{sgroups.p, &ilsched, ngroups, xi64.p};
+            launch_prec_apply<double>(P, P.d64.p, K.B.off.p, ns, mask, x, y, ws64.p, ys64.p, tw64.p, st, &il);
+        };
+        o.apply_i = [this, csign](double *y, const int32_t *mask) {
+            launch_spmv_group_i<double>(mat64.p, K.B.off.p, sgroups.p, gsched, ngroups, mask, xi64.p, y, csign, st);
+        };
+    }
     o.prec = [this, csign, pkind](const double *x, double *y, const int32_t *mask) {
         if (!prec_ready) fail(THM_EINVAL, "preconditioner used before it was built");
         launch_prec_apply<double>(P, P.d64.p, K.B.off.p, ns, mask, x, y, ws64.p, ys64.p, tw64.p, st);
@@ -917,6 +954,16 @@ KOps<float> Ctx::ops32(float csign, bool with_prec, int pkind) {
     o.prec = [this, csign, pkind](const float *x, float *y, const int32_t *mask) {
         prec32(pkind, csign, x, y, mask);
     };
+    if (with_prec && pkind == 0 && lpr32 == SPMV_SELL_GROUP_IL && spmv_shared) {
+        ensure_xi(true);
+        o.prec_i = [this](const float *x, float *y, const int32_t *mask) {
+            const IlOut<float> il{sgroups.p, &ilsched, ngroups, xi32.p};
+            launch_prec_apply<float>(P, P.d32.p, K.B.off.p, ns, mask, x, y, ws32.p, ys32.p, tw32.p, st, &il);
+        };
+        o.apply_i = [this, csign](float *y, const int32_t *mask) {
+            launch_spmv_group_i<float>(mat32.p, K.B.off.p, sgroups.p, gsched, ngroups, mask, xi32.p, y, csign, st);
+        };
+    }
     o.graphable = true;
     o.owner = this;
     o.csign = csign;

@@ -144,6 +144,10 @@ struct KOps {
     std::function<void(const T *x, T *y, const T *b, const int32_t *mask)> apply;
     // y = P^{-1} x
     std::function<void(const T *x, T *y, const int32_t *mask)> prec;
+    // optional pair for the Arnoldi step of a batch with shared-K groups: prec_i is prec that
+    // also writes the member-interleaved copy of y, and apply_i is y = A x reading x from it
+    std::function<void(const T *x, T *y, const int32_t *mask)> prec_i;
+    std::function<void(T *y, const int32_t *mask)> apply_i;
     bool graphable = false;
     const void *owner = nullptr;  // identity of the operator (graph cache key)
     float csign = 1.f;
@@ -192,6 +196,11 @@ struct Ctx {
     Sched gsched;
     int ngroups = 0;
     bool spmv_shared = false;  // some group has two or more members
+    int64_t xi_total = 0;      // complex entries of the member-interleaved copy (see SpmvGroup::xoff)
+    Sched ilsched;             // blocks of the preconditioner's interleaved output, per group
+    DBuf<double> xi64;
+    DBuf<float> xi32;
+    void ensure_xi(bool f32);  // allocates (and zeroes) the interleaved copy of one precision
     void build_groups();
     // y = A x or y = b - A x with SpMV variant v (a code of launch_spmv or SPMV_SELL_GROUP)
     template <class T> void spmv(int v, const int32_t *mask, const T *x, T *y, const T *b, float csign);

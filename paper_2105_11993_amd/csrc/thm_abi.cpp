@@ -665,12 +665,12 @@ struct DdmRun {
         int maxit = 0;
         if (batched) {
             Ctx &c = *D.inner;
-            for (int s = 0; s < ns; ++s) {
-                double *bs = c.b64.p + c.K.B.h_off[s];
-                if (incident)
-                    THM_HIP(hipMemcpyAsync(bs, G.subs[s]->rhs.p, sizeof(double) * 2 * G.subs[s]->n,
-                                           hipMemcpyDeviceToDevice, c.st));
-                else THM_HIP(hipMemsetAsync(bs, 0, sizeof(double) * 2 * G.subs[s]->n, c.st));
+            if (incident) {
+                for (int s = 0; s < ns; ++s)
+                    THM_HIP(hipMemcpyAsync(c.b64.p + c.K.B.h_off[s], G.subs[s]->rhs.p,
+                                           sizeof(double) * 2 * G.subs[s]->n, hipMemcpyDeviceToDevice, c.st));
+            } else {
+                THM_HIP(hipMemsetAsync(c.b64.p, 0, sizeof(double) * c.b64.n, c.st));  // every slot at once
             }
             if (Gv) launch_ddm_rhs(D.ntouch, D.touch_sys.p, D.touch_dof.p, D.touch_ptr.p, D.touch_src.p, D.Bb.p, Gv, c.st);
             THM_HIP(hipMemsetAsync(c.x64.p, 0, sizeof(double) * c.x64.n, c.st));
@@ -1361,7 +1361,7 @@ thm_status thm_time_spmv_batch(thm_system *sys, int32_t precision, int32_t varia
         if (precision != THM_FP64 && precision != THM_FP32_IR) fail(THM_EINVAL, "unknown precision");
         if (!sys->ddm || !sys->ddm->inner) fail(THM_EINVAL, "no subdomain batch yet: run thm_ddm_solve first");
         static const int known[] = {21, 41, 81, 161, 321, 641, 24, 44, 84, 164, 324, THM_SPMV_SELL,
-                                    THM_SPMV_SELL_GROUP};
+                                    THM_SPMV_SELL_GROUP, THM_SPMV_SELL_GROUP_IL};
         bool ok = variant == -1;
         for (int k : known) ok = ok || k == variant;
         if (!ok) fail(THM_EINVAL, "unknown SpMV variant");
@@ -1374,7 +1374,17 @@ thm_status thm_time_spmv_batch(thm_system *sys, int32_t precision, int32_t varia
         hipEvent_t e0, e1;
         THM_HIP(hipEventCreate(&e0));
         THM_HIP(hipEventCreate(&e1));
+        if (v == THM_SPMV_SELL_GROUP_IL) c.ensure_xi(f32);
         auto once = [&] {
+            if (v == THM_SPMV_SELL_GROUP_IL) {
+                if (f32)
+                    launch_spmv_group_i<float>(c.mat32.p, c.K.B.off.p, c.sgroups.p, c.gsched, c.ngroups, nullptr,
+                                               c.xi32.p, c.b32.p, 1.f, c.st);
+                else
+                    launch_spmv_group_i<double>(c.mat64.p, c.K.B.off.p, c.sgroups.p, c.gsched, c.ngroups, nullptr,
+                                                c.xi64.p, c.r64.p, 1.f, c.st);
+                return;
+            }
             if (f32) c.spmv<float>(v, nullptr, c.x32.p, c.b32.p, nullptr, 1.f);
             else c.spmv<double>(v, nullptr, c.x64.p, c.r64.p, nullptr, 1.f);
         };
@@ -1460,6 +1470,7 @@ thm_status thm_time_spmv_systems(int32_t nsys, thm_system *const *sys, int32_t p
 }
 
 static_assert(THM_NOALLOC_SCRATCH_BYTES == thm::NOALLOC_SCRATCH_BYTES, "scratch size of the header and the library");
+static_assert(THM_SPMV_SELL_GROUP_IL == thm::SPMV_SELL_GROUP_IL, "interleaved grouped SpMV code");
 static_assert(THM_SPMV_SELL == thm::SPMV_SELL && THM_SPMV_SELL_GROUP == thm::SPMV_SELL_GROUP,
               "SpMV variant codes of the header and the kernels differ");
 
@@ -1468,7 +1479,7 @@ thm_status thm_set_spmv_variant(thm_system *sys, int32_t precision, int32_t vari
         if (!sys) fail(THM_EINVAL, "bad arguments");
         if (precision != THM_FP64 && precision != THM_FP32_IR) fail(THM_EINVAL, "unknown precision");
         static const int known[] = {21, 41, 81, 161, 321, 641, 24, 44, 84, 164, 324, THM_SPMV_SELL,
-                                    THM_SPMV_SELL_GROUP};
+                                    THM_SPMV_SELL_GROUP, THM_SPMV_SELL_GROUP_IL};
         bool ok = variant == -1;
         for (int k : known) ok = ok || k == variant;
         if (!ok) fail(THM_EINVAL, "unknown SpMV variant");
@@ -1478,7 +1489,7 @@ thm_status thm_set_spmv_variant(thm_system *sys, int32_t precision, int32_t vari
                 c.autotune();
                 return;
             }
-            if (variant != THM_SPMV_SELL_GROUP) c.K.B.spmv_sched(variant, c.st);
+            if (variant != THM_SPMV_SELL_GROUP && variant != THM_SPMV_SELL_GROUP_IL) c.K.B.spmv_sched(variant, c.st);
             if (precision == THM_FP64) c.lpr64 = variant;
             else c.lpr32 = variant;
         };

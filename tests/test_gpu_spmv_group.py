@@ -1,8 +1,9 @@
 """The grouped SELL-64 product of a batch (systems with the same K read it once per
 product, each applies its own C): on a homogeneous partition the subdomains off the x = 0
-side form one group, and the DDM solution with the grouped product is bitwise the one with
-the per-system SELL-64 product (the sums run in the same order) and equals the global LU
-solution; on a partition with random mu every subdomain is its own group and the result
+side form one group, and the DDM solution with the grouped product -- also in the form whose
+Arnoldi steps read the member-interleaved copy that the preconditioner writes -- is bitwise
+the one with the per-system SELL-64 product (the sums run in the same order) and equals the
+global LU solution; on a partition with random mu every subdomain is its own group and the result
 still equals the oracle's.  The single-system form is covered with every other variant in
 test_every_spmv_variant_matches_oracle.
 
@@ -47,9 +48,13 @@ def test_grouped_product_is_bitwise_sell_on_homogeneous_partition(thm, fp32):
     E19, st19 = _solve_pinned(thm, S, thm.THM_SPMV_SELL, o)
     E20, st20 = _solve_pinned(thm, S, thm.THM_SPMV_SELL_GROUP, o)
     assert S.fresh_info()["ddm_spmv_variant"] == thm.THM_SPMV_SELL_GROUP
+    # the Arnoldi steps with the preconditioner writing the member-interleaved copy
+    E29, st29 = _solve_pinned(thm, S, thm.THM_SPMV_SELL_GROUP_IL, o)
+    assert S.fresh_info()["ddm_spmv_variant"] == thm.THM_SPMV_SELL_GROUP_IL
     assert st19["rel_residual"] <= (1e-10 if fp32 else 1e-12) and st20["rel_residual"] == st19["rel_residual"]
     assert st19["iters"] == st20["iters"] and st19["outer_iters"] == st20["outer_iters"]
-    assert np.array_equal(E19, E20)
+    assert st29["iters"] == st20["iters"] and st29["rel_residual"] == st20["rel_residual"]
+    assert np.array_equal(E19, E20) and np.array_equal(E20, E29)
     Eg = system.solve_lu(system.assemble(problem(d)))
     assert rel(E20, Eg) <= (1e-8 if fp32 else 1e-10)
 
@@ -104,7 +109,7 @@ def test_batched_spmv_timing_counts_each_distinct_k_once(thm):
     for prec, w in ((thm.THM_FP64, 8), (thm.THM_FP32_IR, 4)):
         ref = 2 * ((w + 4) * nk + 4 * (subs[0].n + 1))
         ref += sum((w + 4) * c_pattern(s) + 4 * (s.n + 1) + 4 * s.n * w for s in subs)
-        for v in (thm.THM_SPMV_SELL, thm.THM_SPMV_SELL_GROUP):
+        for v in (thm.THM_SPMV_SELL, thm.THM_SPMV_SELL_GROUP, thm.THM_SPMV_SELL_GROUP_IL):
             ms, by = thm.thm_time_spmv_batch(S, prec, v, reps=3)
             print(f"  prec {prec} variant {v}: {ms * 1e3:.1f} us, {by / 1e6:.3f} MB (oracle sizes {ref / 1e6:.3f})",
                   flush=True)
