@@ -749,19 +749,24 @@ __global__ void k_arnoldi_finish(int ns, const int32_t *__restrict__ blkoff, con
     __syncthreads();
     double *gs = g + (int64_t)s * 2 * (m + 1);
     if (threadIdx.x == 0) {
-        double br = hn, bi = 0.0;  // entry j+1 of the column (real on input)
+        const double br = hn, bi = 0.0;  // entry j+1 of the column (real on input)
         colr[j + 1] = br;
         coli[j + 1] = bi;
+        // The rotated entry i+1 of one rotation is entry i of the next: it stays in registers,
+        // so the chain of rotations carries no LDS store-to-load round trip.
+        double xr = colr[0], xi = coli[0];
         for (int i = 0; i < j; ++i) {
             const double c = csl[i], sr = snr[i], si = sni[i];
-            const double ar = colr[i], ai = coli[i], cr = colr[i + 1], ci = coli[i + 1];
+            const double ar = xr, ai = xi, cr = colr[i + 1], ci = coli[i + 1];
             // t = c a + s b ;  b' = -conj(s) a + c b
             colr[i] = c * ar + (sr * cr - si * ci);
             coli[i] = c * ai + (sr * ci + si * cr);
-            colr[i + 1] = -(sr * ar + si * ai) + c * cr;
-            coli[i + 1] = -(sr * ai - si * ar) + c * ci;
+            xr = -(sr * ar + si * ai) + c * cr;
+            xi = -(sr * ai - si * ar) + c * ci;
         }
-        const double ar = colr[j], ai = coli[j], bnr = colr[j + 1], bni = coli[j + 1];
+        colr[j] = xr;
+        coli[j] = xi;
+        const double ar = xr, ai = xi, bnr = colr[j + 1], bni = coli[j + 1];
         const double na = hypot(ar, ai), nb = hypot(bnr, bni);
         const double den = hypot(na, nb);
         double c = 1.0, sr = 0.0, si = 0.0, rr = ar, ri = ai;

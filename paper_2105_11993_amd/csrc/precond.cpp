@@ -1,8 +1,9 @@
 // Setup of the block preconditioner diag(K, K)^{-1} (eq. (11)) as an exact
 // factorised K^{-1}: static condensation of cell interiors, then block cyclic
-// reduction over the layers of skeleton DoFs.  The paper approximates K^{-1} by an
-// AMG with direct level transitions; here the inverse is exact, so GMRES sees the
-// preconditioned operator I + [[0, -K^{-1}C], [K^{-1}C, 0]].
+// reduction over the layers of skeleton DoFs (thin layers), or block LU (thick layers,
+// see plan_lu).  The paper approximates K^{-1} by an AMG with direct level transitions;
+// here the inverse is exact, so GMRES sees the preconditioned operator
+// I + [[0, -K^{-1}C], [K^{-1}C, 0]].
 //
 // Cyclic reduction on the block-tridiagonal skeleton matrix (diagonal blocks D_i,
 // couplings Lo_i between position i and i-1): at every level the odd positions p
@@ -18,6 +19,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <map>
+#include <string>
 
 #include "solver.h"
 
@@ -62,6 +64,33 @@ struct Work {
     double *d_ptr(int layer) { return D.p + rep->L.sinv_off[layer]; }
 };
 }  // namespace
+
+// Padded copies for the apply: each input segment starts at its layer's aligned width,
+// the row length is padded to a multiple of the MFMA column step and the row count to a
+// multiple of the row tile; stored tile by tile (see k_repack).
+static void pad_blocks(Factor &f) {
+    int64_t poff = 0;
+    auto pad = [&](Factor::Blk &b) {
+        int c = 0;
+        for (int q = 0; q < b.nseg; ++q) {
+            b.seg_pstart[q] = c;
+            const int k = b.seg_layer[q];
+            c += (int)(f.pboff[k + 1] - f.pboff[k]);
+        }
+        b.seg_pstart[b.nseg] = c;
+        b.ld = (c + BCR_KS - 1) / BCR_KS * BCR_KS;
+        if (b.ld > 8 * BCR_TAB)
+            fail(THM_EUNSUPPORTED, "a factor block has more columns than the apply kernel supports");
+        b.poff = poff;
+        poff += (int64_t)(b.rows + BCR_RT - 1) / BCR_RT * BCR_RT * b.ld;
+    };
+    for (auto &lev : f.fwd)
+        for (auto &b : lev) pad(b);
+    for (auto &lev : f.bwd)
+        for (auto &b : lev) pad(b);
+    for (auto &b : f.tops) pad(b);
+    f.matp_elems = poff;
+}
 
 // Plan the level structure of one factor and the offsets of its apply matrices.
 static void plan(Factor &f) {
@@ -153,30 +182,74 @@ static void plan(Factor &f) {
     }
     off += (int64_t)f.top_n * f.top_n;
     f.mat_elems = off;
-    // padded copies for the apply: each input segment starts at its layer's aligned
-    // width, the row length is padded to a multiple of the MFMA column step and the row
-    // count to a multiple of the row tile; stored tile by tile (see k_repack)
-    int64_t poff = 0;
-    auto pad = [&](Factor::Blk &b) {
-        int c = 0;
-        for (int q = 0; q < b.nseg; ++q) {
-            b.seg_pstart[q] = c;
-            const int k = b.seg_layer[q];
-            c += (int)(f.pboff[k + 1] - f.pboff[k]);
-        }
-        b.seg_pstart[b.nseg] = c;
-        b.ld = (c + BCR_KS - 1) / BCR_KS * BCR_KS;
-        if (b.ld > 8 * BCR_TAB)
-            fail(THM_EUNSUPPORTED, "a cyclic-reduction block has more columns than the apply kernel supports");
-        b.poff = poff;
-        poff += (int64_t)(b.rows + BCR_RT - 1) / BCR_RT * BCR_RT * b.ld;
-    };
-    for (auto &lev : f.fwd)
-        for (auto &b : lev) pad(b);
-    for (auto &lev : f.bwd)
-        for (auto &b : lev) pad(b);
-    for (auto &b : f.tops) pad(b);
-    f.matp_elems = poff;
+    pad_blocks(f);
+}
+
+// Plan of the block-LU form (thick layers): forward task i computes
+//   y_i = S_i^{-1} r_i - (S_i^{-1} Lo_i) y_{i-1}        (matrix [S_i^{-1} | -S_i^{-1} Lo_i]),
+// backward task i (from the last but one layer down) computes
+//   x_i = y_i - (S_i^{-1} Lo_{i+1}^T) x_{i+1}          (subtracting task),
+// with the block pivots S_0 = D_0, S_i = D_i - Lo_i S_{i-1}^{-1} Lo_i^T.  One forward and one
+// backward level per layer, one task each; no dense last system.
+static void plan_lu(Factor &f) {
+    const int nL = f.nlayers;
+    int64_t off = 0;
+    f.fwd.clear();
+    f.bwd.clear();
+    f.fw_at.clear();
+    f.bk_at.clear();
+    f.level_pos.clear();
+    f.tops.clear();
+    f.top_pos.clear();
+    f.top_n = 0;
+    for (int i = 0; i < nL; ++i) {
+        Factor::Blk b{};
+        b.layer = i;
+        b.rows = f.bsize[i];
+        b.cols = f.bsize[i] + (i > 0 ? f.bsize[i - 1] : 0);
+        b.off = off;
+        off += (int64_t)b.rows * b.cols;
+        b.nseg = 0;
+        b.seg_layer[b.nseg] = i; b.seg_src[b.nseg++] = 0;
+        if (i > 0) { b.seg_layer[b.nseg] = i - 1; b.seg_src[b.nseg++] = 1; }
+        b.out_dst = 1;
+        b.subtract = 0;
+        f.fwd.push_back({b});
+    }
+    for (int i = 0; i + 1 < nL; ++i) {
+        Factor::Blk b{};
+        b.layer = i;
+        b.rows = f.bsize[i];
+        b.cols = f.bsize[i + 1];
+        b.off = off;
+        off += (int64_t)b.rows * b.cols;
+        b.nseg = 0;
+        b.seg_layer[b.nseg] = i + 1; b.seg_src[b.nseg++] = 1;
+        b.out_dst = 1;
+        b.subtract = 1;
+        f.bwd.push_back({b});
+    }
+    f.top_off = off;
+    f.mat_elems = off;
+    pad_blocks(f);
+}
+
+// Cyclic reduction keeps about 5 b^2 words per layer of width b and applies them in
+// 2 log2(layers) + 1 launches; block LU keeps 3 b^2 and needs 2 layers - 1 launches.  With
+// thick layers (3D) each block-LU launch is large enough to stream at full rate, so block LU
+// reads fewer bytes for the same K^{-1}; thin layers (2D) keep cyclic reduction.
+// THM_FACTOR_FORM=bcr|lu overrides the choice (tests of both forms on small problems).
+constexpr int LU_MIN_LAYER = 2048;
+static bool use_block_lu(const Layering &L) {
+    if (const char *e = std::getenv("THM_FACTOR_FORM")) {
+        const std::string v(e);
+        if (v == "lu") return true;
+        if (v == "bcr") return false;
+        fail(THM_EINVAL, "THM_FACTOR_FORM must be bcr or lu");
+    }
+    int64_t wide = 0;
+    for (int32_t b : L.bsize) wide = std::max<int64_t>(wide, b);
+    return wide >= LU_MIN_LAYER;
 }
 
 void setup_precond(const std::vector<thm_system *> &all, hipStream_t st, bool share) {
@@ -205,7 +278,7 @@ void setup_precond(const std::vector<thm_system *> &all, hipStream_t st, bool sh
     DBuf<int32_t> status(1);
     THM_HIP(hipMemsetAsync(status.p, 0, sizeof(int32_t), st));
     std::vector<Work> W(facs.size());
-    int maxlev = 0;
+    int maxlev = 0, maxn_lu = 0;
     for (size_t g = 0; g < facs.size(); ++g) {
         thm_system &R = *reps[g];
         Factor &f = *facs[g];
@@ -219,8 +292,14 @@ void setup_precond(const std::vector<thm_system *> &all, hipStream_t st, bool sh
         f.n_int = t.n_int;
         f.ne = t.n_loc - t.n_int;
         f.n_cells = t.n_cells;
-        plan(f);
-        maxlev = std::max(maxlev, (int)f.fwd.size());
+        f.lu = use_block_lu(L);
+        if (f.lu) {
+            plan_lu(f);
+            maxn_lu = std::max(maxn_lu, f.nlayers);
+        } else {
+            plan(f);
+            maxlev = std::max(maxlev, (int)f.fwd.size());
+        }
         W[g].rep = &R;
         W[g].f = &f;
         // condensation of cell interiors
@@ -257,11 +336,13 @@ void setup_precond(const std::vector<thm_system *> &all, hipStream_t st, bool sh
     DBuf<GemmDesc> gscr;
     Sched gsched;
     auto run_gemms = [&](const std::vector<GemmDesc> &g) {
+        if (g.empty()) return;
         launch_gemm_batched(g, st, gscr, gsched);
         THM_HIP(hipStreamSynchronize(st));
     };
     // inversion scratch
     auto invert = [&](std::vector<std::pair<const double *, std::pair<double *, int>>> jobs, const std::vector<int> &ns) {
+        if (jobs.empty()) return;
         int64_t tot = 0, totp = 0;
         for (int n : ns) { tot += 2 * (int64_t)n * n; totp += 2 * n; }
         DBuf<double> work(std::max<int64_t>(tot, 1));
@@ -292,7 +373,7 @@ void setup_precond(const std::vector<thm_system *> &all, hipStream_t st, bool sh
         // 1. inverses of the odd positions (into the first columns of their back-substitution blocks)
         for (Work &w : W) {
             Factor &f = *w.f;
-            if (lev >= (int)f.fwd.size()) continue;
+            if (f.lu || lev >= (int)f.fwd.size()) continue;
             const auto &pos = f.level_pos[lev];
             for (int i = 1; i < (int)pos.size(); i += 2) {
                 const Factor::Blk &b = f.bwd[lev][f.bk_at[lev].at(i)];
@@ -304,7 +385,7 @@ void setup_precond(const std::vector<thm_system *> &all, hipStream_t st, bool sh
         // 2. Gm, Gp; 3. D updates and new couplings
         for (Work &w : W) {
             Factor &f = *w.f;
-            if (lev >= (int)f.fwd.size()) continue;
+            if (f.lu || lev >= (int)f.fwd.size()) continue;
             const auto &pos = f.level_pos[lev];
             const int m = (int)pos.size();
             for (int i = 0; i < m; i += 2) {
@@ -343,7 +424,7 @@ void setup_precond(const std::vector<thm_system *> &all, hipStream_t st, bool sh
         // 4. back-substitution couplings: -Gp_{p-1}^T and -Gm_{p+1}^T next to Dinv_p
         for (Work &w : W) {
             Factor &f = *w.f;
-            if (lev >= (int)f.fwd.size()) continue;
+            if (f.lu || lev >= (int)f.fwd.size()) continue;
             const auto &pos = f.level_pos[lev];
             const int m = (int)pos.size();
             for (int i = 1; i < m; i += 2) {
@@ -362,6 +443,44 @@ void setup_precond(const std::vector<thm_system *> &all, hipStream_t st, bool sh
         THM_HIP(hipStreamSynchronize(st));
         for (LoNew &ln : lonew) ln.w->lo[ln.layer] = std::move(ln.buf);
     }
+    // block LU, one layer at a time over every block-LU factor
+    for (int i = 0; i < maxn_lu; ++i) {
+        if (progress) std::fprintf(stderr, "[thm]   block-LU layer %d at %.1f ms\n", i, now_ms() - t0);
+        std::vector<GemmDesc> ga, gb, gd;
+        std::vector<std::pair<const double *, std::pair<double *, int>>> jobs;
+        std::vector<int> jn;
+        for (Work &w : W) {
+            Factor &f = *w.f;
+            if (!f.lu || i >= f.nlayers || i == 0) continue;
+            const int b = f.bsize[i], bl = f.bsize[i - 1];
+            const Factor::Blk &fl = f.fwd[i - 1][0], &bk = f.bwd[i - 1][0];
+            // backward matrix of layer i-1: S_{i-1}^{-1} Lo_i^T (Lo_i is b x bl)
+            ga.push_back({bl, b, bl, 0, 1, f.mat.p + fl.off, w.lo_ptr(i), f.mat.p + bk.off, fl.cols, bl, b, 1.0, 0.0});
+            // pivot S_i = D_i - Lo_i (S_{i-1}^{-1} Lo_i^T)
+            gb.push_back({b, b, bl, 0, 0, w.lo_ptr(i), f.mat.p + bk.off, w.d_ptr(i), bl, b, b, -1.0, 1.0});
+        }
+        run_gemms(ga);
+        run_gemms(gb);
+        for (Work &w : W) {
+            Factor &f = *w.f;
+            if (!f.lu || i >= f.nlayers) continue;
+            const Factor::Blk &fb = f.fwd[i][0];
+            jobs.push_back({w.d_ptr(i), {f.mat.p + fb.off, fb.cols}});
+            jn.push_back(fb.rows);
+        }
+        invert(jobs, jn);
+        THM_HIP(hipStreamSynchronize(st));
+        for (Work &w : W) {
+            Factor &f = *w.f;
+            if (!f.lu || i >= f.nlayers || i == 0) continue;
+            const int b = f.bsize[i], bl = f.bsize[i - 1];
+            const Factor::Blk &fb = f.fwd[i][0];
+            // second block of the forward matrix: -S_i^{-1} Lo_i
+            gd.push_back({b, bl, b, 0, 0, f.mat.p + fb.off, w.lo_ptr(i), f.mat.p + fb.off + b, fb.cols, bl, fb.cols,
+                          -1.0, 0.0});
+        }
+        run_gemms(gd);
+    }
     // last blocks: assemble the remaining block-tridiagonal system densely and invert it
     {
         std::vector<std::pair<const double *, std::pair<double *, int>>> jobs;
@@ -370,6 +489,7 @@ void setup_precond(const std::vector<thm_system *> &all, hipStream_t st, bool sh
         for (size_t g = 0; g < W.size(); ++g) {
             Work &w = W[g];
             Factor &f = *w.f;
+            if (f.lu) continue;
             const int N = f.top_n;
             dense[g].alloc((size_t)N * N);
             launch_fill(dense[g].p, (int64_t)N * N, 0.0, st);

@@ -14,6 +14,7 @@ struct Ddm;
 // systems with identical matrices.
 struct Factor {
     int nlayers = 0;
+    bool lu = false;             // block-LU form (thick layers) instead of cyclic reduction
     std::vector<int32_t> bsize;
     std::vector<int64_t> boff;
     int n_int = 0, ne = 0;
@@ -39,7 +40,8 @@ struct Factor {
     std::vector<std::map<int, int>> fw_at, bk_at;
     std::vector<std::vector<int>> level_pos;
     // The reduction stops when few blocks remain; their block-tridiagonal system is
-    // inverted densely and applied as one phase (one task per block row).
+    // inverted densely and applied as one phase (one task per block row).  The block-LU
+    // form has one task per forward and backward level and no dense last system.
     std::vector<Blk> tops;
     std::vector<int> top_pos;
     int64_t top_off = 0;

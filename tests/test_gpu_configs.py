@@ -130,19 +130,25 @@ def test_c3_ddm_16(thm):
     assert rel(E, Eg) <= 1e-10
 
 
-def test_c3_subdomain_factor_backward_error(thm):
+@pytest.mark.parametrize("form", ["auto", "bcr"])
+def test_c3_subdomain_factor_backward_error(thm, form, monkeypatch):
     """The exact K^{-1} at the shape of one 32^3-recipe subdomain (16^3 hexes, degree 1:
-    17 layers of 4,866 skeleton DoFs, cyclic reduction down to one dense last block), with the
-    recipe's random mu: normwise backward error of K z = x in FP64 and FP32, against the
-    oracle's assembled K.  The explicit inverses of 4,866-wide indefinite pivot blocks grow
-    rounding by about 5e5 here (measured 5.9e-11 in FP64, 2.4e-3 in FP32, against 5e-13 on the
-    small 3D shapes): the bars leave a factor of 10 over that and still fail on a missing,
-    misplaced or wrongly signed tile (an O(1) error).  This FP32 backward error is why 3D
-    mixed precision refines with GMRES-IR rather than with FP32 inner solves."""
+    17 layers of 4,866 skeleton DoFs), in the form the library picks for such thick layers
+    (block LU) and as cyclic reduction down to one dense last block, with the recipe's random
+    mu: normwise backward error of K z = x in FP64 and FP32, against the oracle's assembled K.
+    The explicit inverses of 4,866-wide indefinite pivot blocks grow rounding by about 5e5 here
+    (cyclic reduction: 5.9e-11 in FP64, 2.4e-3 in FP32, against 5e-13 on the small 3D shapes):
+    the bars leave a factor of 10 over that and still fail on a missing, misplaced or wrongly
+    signed tile (an O(1) error).  This FP32 backward error is why 3D mixed precision refines
+    with GMRES-IR rather than with FP32 inner solves."""
     import torch
     from tests._gpu_helpers import dirichletized
+    if form == "auto":
+        monkeypatch.delenv("THM_FACTOR_FORM", raising=False)
+    else:
+        monkeypatch.setenv("THM_FACTOR_FORM", form)
     d = dict(workloads.c3(m=16), subdomains=(1, 1, 1))
-    print("case cyclic reduction 16^3 p1", flush=True)
+    print("case factor 16^3 p1", form, flush=True)
     S = thm.thm_assemble(d)
     assert S.info["n_layers"] == 17
     so = system.assemble(problem(d))
@@ -157,7 +163,7 @@ def test_c3_subdomain_factor_backward_error(thm):
 
     e64 = eta(thm.thm_apply_precond(S, xt).cpu().numpy())
     e32 = eta(thm.thm_apply_precond(S, xt, precision=thm.THM_FP32_IR).cpu().numpy())
-    print(f"16^3 factor backward error: fp64 {e64:.2e} fp32 {e32:.2e}", flush=True)
+    print(f"16^3 factor ({form}) backward error: fp64 {e64:.2e} fp32 {e32:.2e}", flush=True)
     assert e64 <= 1e-9
     assert e32 <= 3e-2
 
