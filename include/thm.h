@@ -243,7 +243,12 @@ const char *thm_last_error(void);
  * operator (x, y still complex128). */
 thm_status thm_apply_operator(thm_system *sys, int32_t transpose, int32_t precision,
                               const void *x_dev, void *y_dev, void *stream);
-/* y = diag(K, K)^{-1} x (eq. (11)), exact factorised inverse; factorises on first use. */
+/* y = diag(K, K)^{-1} x (eq. (11)), exact factorised inverse; factorises on first use.  After
+ * static condensation of cell interiors, K's skeleton is block tridiagonal over layers of the
+ * mesh; it is factorised by block cyclic reduction when its layers are thin (below 2048
+ * skeleton DoFs, e.g. 2D meshes) and by block LU when they are thick (3D).  The environment
+ * variable THM_FACTOR_FORM = "bcr" or "lu", read when a factorisation is built, forces one
+ * form (any other value: THM_EINVAL). */
 thm_status thm_apply_precond(thm_system *sys, int32_t precision, const void *x_dev, void *y_dev,
                              void *stream);
 /* y = (K + iC)^{-1} x (transpose = 0) or (K - iC)^{-1} x (transpose = 1): the complete
@@ -314,8 +319,8 @@ thm_status thm_time_spmv_systems(int32_t nsys, thm_system *const *sys, int32_t p
  * Returns THM_EINVAL for an unknown variant or precision. */
 thm_status thm_set_spmv_variant(thm_system *sys, int32_t precision, int32_t variant);
 
-/* Average device time (ms) of `reps` applications of the block cyclic-reduction
- * phases of the preconditioner (eq. (11)) -- the DDM's batched subdomain context if a
+/* Average device time (ms) of `reps` applications of the factor phases (block cyclic
+ * reduction or block LU) of the preconditioner (eq. (11)) -- the DDM's batched subdomain context if a
  * DDM solve has run on `sys`, else the system's own -- measured with HIP events on the
  * library's stream.  bytes_out: algorithmic bytes per application (every factor matrix
  * once plus member vectors); launches_out: kernel launches per application. */
