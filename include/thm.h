@@ -245,8 +245,8 @@ thm_status thm_apply_operator(thm_system *sys, int32_t transpose, int32_t precis
                               const void *x_dev, void *y_dev, void *stream);
 /* y = diag(K, K)^{-1} x (eq. (11)), exact factorised inverse; factorises on first use.  After
  * static condensation of cell interiors, K's skeleton is block tridiagonal over layers of the
- * mesh; it is factorised by block cyclic reduction when its layers are thin (below 2048
- * skeleton DoFs, e.g. 2D meshes) and by block LU when they are thick (3D).  The environment
+ * mesh; it is factorised by block LU when there are at most 64 layers and the widest has at
+ * least 1024 skeleton DoFs (3D subdomains), else by block cyclic reduction.  The environment
  * variable THM_FACTOR_FORM = "bcr" or "lu", read when a factorisation is built, forces one
  * form (any other value: THM_EINVAL). */
 thm_status thm_apply_precond(thm_system *sys, int32_t precision, const void *x_dev, void *y_dev,

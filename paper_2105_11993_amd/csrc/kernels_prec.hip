@@ -304,15 +304,18 @@ template <> struct Mfma<double> {
 };
 
 // ------------------------------------------------------------------ batched FP64 GEMM (setup)
-// C = alpha op(A) op(B) + beta C for a batch of matrices: 64 x 64 tiles of C per block, 16-deep
+// C = alpha op(A) op(B) + beta C for a batch of matrices: 64 x 64 tiles of C per block, 32-deep
 // K steps staged through LDS, each wave a 32 x 32 quarter of the tile as 2 x 2 MFMA tiles
-// (v_mfma_f64_16x16x4f64: lane i + 16 g feeds A[i][k0 + g] and B[k0 + g][i]).  The order of
-// the sum over k is fixed, so results are reproducible.
+// (v_mfma_f64_16x16x4f64: lane i + 16 g feeds A[i][k0 + g] and B[k0 + g][i]).  The next K
+// step's operands are loaded into registers while the current one runs on the matrix cores;
+// each operand is read along its contiguous direction (per transpose flag).  The order of the
+// sum over k is fixed (k ascending in steps of 4), so results are reproducible.
+constexpr int GEMM_BK = 32;
 __global__ void __launch_bounds__(256) k_gemm(const GemmDesc *__restrict__ ds, const int32_t *__restrict__ blkoff,
                                               int nd) {
     using V4 = Mfma<double>::v4;
-    __shared__ double As[16][64 + 1];
-    __shared__ double Bs[16][64 + 1];
+    __shared__ double As[GEMM_BK][64 + 1];
+    __shared__ double Bs[GEMM_BK][64 + 1];
     const int di = find_sys2(blkoff, nd, blockIdx.x);
     const GemmDesc d = ds[di];
     const int tiles_n = (d.n + 63) / 64;
@@ -322,37 +325,63 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmDesc *__restrict__ ds, c
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i16 = lane & 15, g = lane >> 4;
     const int wr = 32 * (wave >> 1), wc = 32 * (wave & 1);
+    constexpr int NPT = GEMM_BK * 64 / 256;  // operand values per thread and step
+    // (row, k) of value q of this thread in the A tile and (k, col) in the B tile: consecutive
+    // threads take consecutive addresses of the stored operand
+    auto a_at = [&](int q, int &r, int &kk) {
+        const int e = (int)threadIdx.x + 256 * q;
+        if (d.ta) { r = e % 64; kk = e / 64; } else { r = e / GEMM_BK; kk = e % GEMM_BK; }
+    };
+    auto b_at = [&](int q, int &kk, int &c) {
+        const int e = (int)threadIdx.x + 256 * q;
+        if (d.tb) { kk = e % GEMM_BK; c = e / GEMM_BK; } else { kk = e / 64; c = e % 64; }
+    };
+    double ra[NPT], rb[NPT];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < NPT; ++q) {
+            int r, kk;
+            a_at(q, r, kk);
+            const int gi = row0 + r, gk = k0 + kk;
+            ra[q] = (gi < d.m && gk < d.k) ? (d.ta ? d.A[(int64_t)gk * d.lda + gi] : d.A[(int64_t)gi * d.lda + gk])
+                                           : 0.0;
+            int kb, c;
+            b_at(q, kb, c);
+            const int gk2 = k0 + kb, gj = col0 + c;
+            rb[q] = (gk2 < d.k && gj < d.n) ? (d.tb ? d.B[(int64_t)gj * d.ldb + gk2] : d.B[(int64_t)gk2 * d.ldb + gj])
+                                            : 0.0;
+        }
+    };
     V4 acc[2][2];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = V4{0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < d.k; k0 += 16) {
-        for (int e = threadIdx.x; e < 1024; e += 256) {
-            const int r = e / 16, kk = e % 16;  // A tile: 64 rows x 16 k
-            const int gi = row0 + r, gk = k0 + kk;
-            double v = 0.0;
-            if (gi < d.m && gk < d.k) v = d.ta ? d.A[(int64_t)gk * d.lda + gi] : d.A[(int64_t)gi * d.lda + gk];
-            As[kk][r] = v;
-            const int kb = e / 64, cb = e % 64;  // B tile: 16 k x 64 cols
-            const int gk2 = k0 + kb, gj = col0 + cb;
-            double w = 0.0;
-            if (gk2 < d.k && gj < d.n) w = d.tb ? d.B[(int64_t)gj * d.ldb + gk2] : d.B[(int64_t)gk2 * d.ldb + gj];
-            Bs[kb][cb] = w;
+        for (int y = 0; y < 2; ++y) acc[x][y] = V4{0.0, 0.0, 0.0, 0.0};
+    fetch(0);
+    for (int k0 = 0; k0 < d.k; k0 += GEMM_BK) {
+#pragma unroll
+        for (int q = 0; q < NPT; ++q) {
+            int r, kk;
+            a_at(q, r, kk);
+            As[kk][r] = ra[q];
+            int kb, c;
+            b_at(q, kb, c);
+            Bs[kb][c] = rb[q];
         }
         __syncthreads();
+        if (k0 + GEMM_BK < d.k) fetch(k0 + GEMM_BK);  // in flight while this step runs
 #pragma unroll
-        for (int k4 = 0; k4 < 16; k4 += 4) {
-            double a[2], b[2];
+        for (int k4 = 0; k4 < GEMM_BK; k4 += 4) {
+            double a2[2], b2[2];
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
-                a[t] = As[k4 + g][wr + 16 * t + i16];
-                b[t] = Bs[k4 + g][wc + 16 * t + i16];
+                a2[t] = As[k4 + g][wr + 16 * t + i16];
+                b2[t] = Bs[k4 + g][wc + 16 * t + i16];
             }
 #pragma unroll
             for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-                for (int nt = 0; nt < 2; ++nt) acc[mt][nt] = Mfma<double>::op(a[mt], b[nt], acc[mt][nt]);
+                for (int nt = 0; nt < 2; ++nt) acc[mt][nt] = Mfma<double>::op(a2[mt], b2[nt], acc[mt][nt]);
         }
         __syncthreads();
     }

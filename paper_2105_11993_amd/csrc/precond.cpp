@@ -236,10 +236,13 @@ static void plan_lu(Factor &f) {
 
 // Cyclic reduction keeps about 5 b^2 words per layer of width b and applies them in
 // 2 log2(layers) + 1 launches; block LU keeps 3 b^2 and needs 2 layers - 1 launches.  With
-// thick layers (3D) each block-LU launch is large enough to stream at full rate, so block LU
-// reads fewer bytes for the same K^{-1}; thin layers (2D) keep cyclic reduction.
+// few thick layers (3D subdomains: 9 layers of 1,282 at 8^3, 17 of 4,866 at 16^3) each
+// block-LU launch is large enough to stream at full rate and block LU reads fewer bytes for
+// the same K^{-1}; with many thin layers (2D meshes) the launches are latency-bound and the
+// long chain of pivots is the less accurate one in FP32, so cyclic reduction stays.
 // THM_FACTOR_FORM=bcr|lu overrides the choice (tests of both forms on small problems).
-constexpr int LU_MIN_LAYER = 2048;
+constexpr int LU_MIN_LAYER = 1024;
+constexpr int LU_MAX_LAYERS = 64;
 static bool use_block_lu(const Layering &L) {
     if (const char *e = std::getenv("THM_FACTOR_FORM")) {
         const std::string v(e);
@@ -249,7 +252,7 @@ static bool use_block_lu(const Layering &L) {
     }
     int64_t wide = 0;
     for (int32_t b : L.bsize) wide = std::max<int64_t>(wide, b);
-    return wide >= LU_MIN_LAYER;
+    return wide >= LU_MIN_LAYER && L.nlayers <= LU_MAX_LAYERS;
 }
 
 void setup_precond(const std::vector<thm_system *> &all, hipStream_t st, bool share) {
