@@ -77,3 +77,34 @@ def test_invalid_factor_form_is_rejected(thm, monkeypatch):
     S = thm.thm_assemble(spec(2, 3, 0, 4.0))
     with pytest.raises(thm.ThmError):
         thm.thm_apply_precond(S, torch.zeros(S.n, dtype=torch.complex128, device="cuda"))
+
+
+SMALLEST = [spec(2, 1, p, 3.0) for p in (0, 1, 2, 3)] + [spec(3, 1, p, 2.0) for p in (0, 1)]
+
+
+@pytest.mark.parametrize("d", SMALLEST, ids=_ids)
+def test_block_lu_on_smallest_meshes(thm, d, monkeypatch):
+    """One-cell meshes (two layers): the block-LU factor inverts K, the complete inverse built on
+    it inverts K + iC, and the allocation-free apply gives the same bits as the allocating one."""
+    import torch
+    rng = np.random.default_rng(82)
+    d = dict(d, mu=rng.uniform(1.0, 2.0, d["n"][0] ** d["dim"]))
+    print("case block lu smallest", _ids(d), flush=True)
+    monkeypatch.setenv("THM_FACTOR_FORM", "lu")
+    S = thm.thm_assemble(d)
+    so = system.assemble(problem(d))
+    Sd = dirichletized(so)[0]
+    x = rng.standard_normal(S.n) + 1j * rng.standard_normal(S.n)
+    xt = torch.from_numpy(x).cuda()
+
+    def eta(A, z):
+        an = abs(A).sum(axis=1).max()
+        return np.linalg.norm(A @ z - x, np.inf) / (an * np.linalg.norm(z, np.inf) + np.linalg.norm(x, np.inf))
+
+    z = thm.thm_apply_precond(S, xt)
+    assert eta(Sd.real, z.cpu().numpy()) <= 1e-12
+    assert eta(Sd, thm.thm_apply_precond_full(S, xt).cpu().numpy()) <= 1e-12
+    y = torch.full_like(xt, complex(float("nan"), float("nan")))
+    thm.thm_apply_precond_noalloc(S, xt, y)
+    torch.cuda.synchronize()
+    assert np.array_equal(y.cpu().numpy(), z.cpu().numpy())
