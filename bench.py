@@ -60,6 +60,8 @@ def parse():
                     help="1: relax the subdomain tolerance as the outer residual falls (inexact Krylov, scaled by "
                          "the outer Hessenberg's smallest singular value; the final global FP64 residual still "
                          "meets 1e-8); 0: fixed inner tolerance")
+    ap.add_argument("--ir-inner-rtol", type=float, default=1e-6,
+                    help="relative tolerance of each FP32 inner solve of a refinement step")
     ap.add_argument("--ir-mode", choices=["classic", "gmres"], default=None,
                     help="refinement of the FP32 forms: classic (FP32 inner GMRES cycles, the default) or gmres "
                          "(GMRES-IR: FP64 GMRES preconditioned by the FP32 factor)")
@@ -67,7 +69,7 @@ def parse():
     ap.add_argument("--c3-block-outer", type=int, default=2,
                     help="c3: outer steps of the block-preconditioned forms (capped; 0 = skip)")
     ap.add_argument("--c3-mixed-full", action="store_true",
-                    help="c3: also time GMRES-IR with the FP32 complete inverse")
+                    help="c3: also time the FP32 complete inverse with FP64 refinement (--ir-mode picks the form)")
     ap.add_argument("--c3-block-timed", action="store_true",
                     help="c3: time the block-preconditioned forms to 1e-8 like the 2D line (small meshes)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -273,7 +275,7 @@ def c4_leg(args, thm, torch, workloads, scale, steps=1, warmup=1):
     n_tot = sum(s.n for s in systems)
     log(args, f"c4: assembled {len(systems)} problems, {n_tot} DoFs in {t_asm:.2f}s")
     common = dict(rtol=1e-8, restart=args.c4_restart, max_iter=20000)
-    fast = thm.default_opts(precision=thm.THM_FP32_IR, batched=1, use_graph=1, ir_inner_rtol=1e-6, **common)
+    fast = thm.default_opts(precision=thm.THM_FP32_IR, batched=1, use_graph=1, ir_inner_rtol=args.ir_inner_rtol, **common)
     b64 = thm.default_opts(precision=thm.THM_FP64, batched=1, use_graph=1, **common)
     plain = thm.default_opts(precision=thm.THM_FP64, batched=0, use_graph=0, **common)
 
@@ -467,7 +469,7 @@ def c3_leg(args, thm, torch, workloads, block_outer=0, mixed_full=None):
     info = S.info
     log(args, f"c3 assembled: n={info['n_dofs']} nnz={info['nnz']} in {t_asm:.2f}s")
     common = dict(rtol=1e-8, inner_rtol=args.inner_rtol, restart=args.restart, max_outer=args.max_outer,
-                  relax_inner=args.relax_inner, batched=1, use_graph=1, ir_inner_rtol=1e-6)
+                  relax_inner=args.relax_inner, batched=1, use_graph=1, ir_inner_rtol=args.ir_inner_rtol)
     full64 = thm.default_opts(precision=thm.THM_FP64, precond=thm.THM_PREC_FULL, **common)
     forms = {}
     fields = {}
@@ -715,7 +717,7 @@ def main():
                   relax_inner=args.relax_inner)
     ir_mode = args.ir_mode or "classic"
     irm = thm.THM_IR_GMRES if ir_mode == "gmres" else thm.THM_IR_CLASSIC
-    fast = thm.default_opts(precision=thm.THM_FP32_IR, batched=1, use_graph=1, ir_inner_rtol=1e-6, ir_mode=irm,
+    fast = thm.default_opts(precision=thm.THM_FP32_IR, batched=1, use_graph=1, ir_inner_rtol=args.ir_inner_rtol, ir_mode=irm,
                             **common)
     batched64 = thm.default_opts(precision=thm.THM_FP64, batched=1, use_graph=1, **common)
     plain = thm.default_opts(precision=thm.THM_FP64, batched=0, use_graph=0, **common)
@@ -767,7 +769,7 @@ def main():
                                          "(THM_PREC_FULL); an ablation, not the benchmark form"}
         stf = None
         for name, prec in (("fp32_refine", thm.THM_FP32_IR), ("fp64", thm.THM_FP64)):
-            of = thm.default_opts(precision=prec, batched=1, use_graph=1, ir_inner_rtol=1e-6, ir_mode=irm,
+            of = thm.default_opts(precision=prec, batched=1, use_graph=1, ir_inner_rtol=args.ir_inner_rtol, ir_mode=irm,
                                   precond=thm.THM_PREC_FULL, **common)
             t0 = time.perf_counter()
             _, stf = thm.thm_ddm_solve(S, of, allow_not_converged=True)  # the first call builds M^{-1}
